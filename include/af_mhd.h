@@ -1,0 +1,136 @@
+/* af_mhd.h -- C ABI of the MI355X (gfx950) library for one SSP-RK3 stage of
+ * the positivity-preserving Active Flux scheme for 2D ideal MHD with the
+ * Godunov-Powell source term (Duan, Chandrashekar, Klingenberg,
+ * arXiv 2506.04857).
+ *
+ * The method: Section 2 (cell-average and point-value updates), Section 3
+ * (first-order LLF scheme, parametrized flux limiter, scaling limiter, shock
+ * sensor), time integration by SSP-RK3 whose stages are convex combinations
+ * of forward-Euler steps (Sections 2 and 3.1).
+ *
+ * Degrees of freedom on an nx x ny Cartesian grid with spacings dx, dy
+ * (0-based; fig. 2d_af_dofs):
+ *   A(i,j)  cell average of cell (i,j)
+ *   X(k,j)  point value at (x_{k-1/2}, y_j)        left vertical face of cell k
+ *   Y(i,l)  point value at (x_i, y_{l-1/2})        bottom horizontal face of cell i
+ *   V(k,l)  point value at (x_{k-1/2}, y_{l-1/2})  lower-left vertex of cell (k,l)
+ * A periodic direction holds n entries per point set, an outflow direction
+ * n+1 (the boundary nodes on both sides).  Conservative variables in the
+ * paper's order U = (rho, rho v1, rho v2, rho v3, B1, B2, B3, E).
+ *
+ * Memory: every array is FP64, structure of arrays, component-major, x
+ * fastest, C-contiguous, in device memory of the current HIP device:
+ *   cell  [8][ny ][nx ]
+ *   xface [8][ny ][nxp]   nxp = nx (periodic x) or nx+1 (outflow x)
+ *   yface [8][nyp][nx ]   nyp = ny (periodic y) or ny+1 (outflow y)
+ *   vert  [8][nyp][nxp]
+ * The caller owns all device memory (states and the workspace); the library
+ * never allocates device memory.  Pointers must be 8-byte aligned.
+ *
+ * Asynchrony: af_mhd_dt, af_mhd_stage and af_mhd_step only enqueue work on
+ * the context's stream and never synchronise; the time step lives in device
+ * memory.  af_mhd_stats synchronises the stream.
+ *
+ * Errors: functions return an af_status; none aborts.  A context is not
+ * thread-safe; several contexts may coexist.
+ */
+#ifndef AF_MHD_H
+#define AF_MHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AF_OK = 0,
+  AF_EINVAL = -1,          /* invalid argument: null/misaligned pointer, bad size, bad k */
+  AF_EHIP = -2,            /* a HIP runtime call failed; see af_mhd_last_error */
+  AF_EWORKSPACE = -3,      /* workspace smaller than af_mhd_workspace_bytes */
+  AF_ENOTADMISSIBLE = -4   /* af_mhd_stats: some degree of freedom is outside G (rho<=0 or p<=0) */
+} af_status;
+
+enum { AF_BC_PERIODIC = 0, AF_BC_OUTFLOW = 1 };
+
+typedef struct {
+  int32_t nx, ny;           /* cells per direction, each >= 4 */
+  double x0, x1, y0, y1;    /* domain; dx = (x1-x0)/nx, dy = (y1-y0)/ny */
+  double gamma;             /* adiabatic index of the perfect gas EOS, > 1 (Section 1) */
+  double cfl;               /* dt = cfl / max over all DoFs of (rho_1/dx + rho_2/dy), in (0,1] */
+  double kappa;             /* shock-sensor strength (Section 3.4), >= 0; 0 disables the sensor */
+  int32_t bc_x, bc_y;       /* AF_BC_PERIODIC or AF_BC_OUTFLOW per direction */
+  uint32_t flags;           /* must be 0 */
+} af_mhd_params;
+
+typedef struct {            /* one state: the four DoF sets (layout above) */
+  double* cell;
+  double* xface;
+  double* yface;
+  double* vert;
+} af_mhd_state;
+
+typedef struct {
+  double min_rho, min_p;    /* over all DoFs of the state */
+  double mass;              /* sum of cell-average densities times dx dy */
+  double min_theta;         /* smallest flux-limiter interface coefficient since init */
+  int64_t n_llf_not_admissible; /* first-order LLF states outside G (Lemma's CFL violated) */
+  int64_t n_newton;         /* vertex root solves of the flux limiter, step (2) */
+  int64_t newton_iters_max;
+  int64_t n_fallback;       /* round-off fallback uses (closing remark of Section 4) */
+  int64_t n_not_admissible; /* stage outputs outside G */
+  int64_t n_theta_active;   /* interfaces with a flux-limiter coefficient < 1 */
+  int64_t n_point_limited;  /* point values changed by the scaling limiter */
+  int64_t n_centre_limited; /* centre values changed by their limiter */
+  int64_t n_source_limited; /* cells whose Powell source was blended towards LLF */
+  int64_t n_dof_not_admissible; /* DoFs of the state passed to af_mhd_stats outside G */
+} af_mhd_stats_t;
+
+typedef struct af_mhd_ctx af_mhd_ctx;  /* opaque host object */
+
+/* Bytes of device workspace the context needs for these parameters (RK
+ * scratch states, stage intermediates, reduction buffers, counters).
+ * Returns 0 for invalid parameters. */
+size_t af_mhd_workspace_bytes(const af_mhd_params* p);
+
+/* Create a context.  workspace_dev: caller-owned device buffer of at least
+ * af_mhd_workspace_bytes(p) bytes, 256-byte aligned, kept alive until
+ * af_mhd_destroy.  hip_stream: a hipStream_t (NULL = the null stream).
+ * Zeroes the counters (asynchronously on the stream).  *out is set only on AF_OK. */
+int af_mhd_init(const af_mhd_params* p, void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                af_mhd_ctx** out);
+
+/* Time step from the state u: dt = min(cfl / max_DoF(rho_1/dx + rho_2/dy),
+ * t_remaining), written to dt_dev (one device double).  t_remaining > 0. */
+int af_mhd_dt(af_mhd_ctx* c, const af_mhd_state* u, double t_remaining, double* dt_dev);
+
+/* One SSP-RK3 stage: out = a_k un + b_k FE(uk, dt) with (a,b) = (0,1),
+ * (3/4,1/4), (1/3,2/3) for k = 0, 1, 2; FE is the limited forward-Euler step
+ * of the scheme (Sections 2-3), dt read from dt_dev.  out must not alias uk;
+ * out may alias un (each output element reads un only at its own index);
+ * for k = 0 un is not read. */
+int af_mhd_stage(af_mhd_ctx* c, int k, const af_mhd_state* un, const af_mhd_state* uk, af_mhd_state* out,
+                 const double* dt_dev);
+
+/* One SSP-RK3 step in place on u: af_mhd_dt then the three stages, using
+ * the workspace's scratch states.  The dt used is left in dt_dev. */
+int af_mhd_step(af_mhd_ctx* c, af_mhd_state* u, double t_remaining, double* dt_dev);
+
+/* Statistics of u and the counters accumulated since af_mhd_init.
+ * Synchronises the stream.  Returns AF_ENOTADMISSIBLE (with *out filled)
+ * when some DoF of u is outside G. */
+int af_mhd_stats(af_mhd_ctx* c, const af_mhd_state* u, af_mhd_stats_t* out);
+
+/* Reset the counters to zero (asynchronously on the stream). */
+int af_mhd_reset_counters(af_mhd_ctx* c);
+
+void af_mhd_destroy(af_mhd_ctx* c);
+
+/* Message of the last error on this context ("" if none); valid until the next call. */
+const char* af_mhd_last_error(const af_mhd_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AF_MHD_H */

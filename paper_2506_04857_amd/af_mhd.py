@@ -1,0 +1,192 @@
+"""Thin Python binding of the HIP library (include/af_mhd.h): argument
+marshalling only.  Every step of the stage runs in libaf_mhd.so; PyTorch
+provides device memory and the stream.  There is no fallback path: if the
+library is missing this module raises on import.
+
+A state is a tuple ``(cell, xface, yface, vert)`` of contiguous float64 CUDA
+(HIP) tensors with shapes ``(8, ny, nx)``, ``(8, ny, nxp)``, ``(8, nyp, nx)``,
+``(8, nyp, nxp)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libaf_mhd.so")
+
+AF_OK, AF_EINVAL, AF_EHIP, AF_EWORKSPACE, AF_ENOTADMISSIBLE = 0, -1, -2, -3, -4
+AF_BC_PERIODIC, AF_BC_OUTFLOW = 0, 1
+
+
+class af_mhd_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+
+class af_mhd_state(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_void_p), ("xface", ctypes.c_void_p), ("yface", ctypes.c_void_p),
+                ("vert", ctypes.c_void_p)]
+
+
+class af_mhd_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("min_rho", ctypes.c_double), ("min_p", ctypes.c_double), ("mass", ctypes.c_double),
+        ("min_theta", ctypes.c_double),
+        ("n_llf_not_admissible", ctypes.c_int64), ("n_newton", ctypes.c_int64),
+        ("newton_iters_max", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
+        ("n_not_admissible", ctypes.c_int64), ("n_theta_active", ctypes.c_int64),
+        ("n_point_limited", ctypes.c_int64), ("n_centre_limited", ctypes.c_int64),
+        ("n_source_limited", ctypes.c_int64), ("n_dof_not_admissible", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is not built; run __graft_entry__.build() "
+                          "or python -m paper_2506_04857_amd.build")
+    L = ctypes.CDLL(path)
+    P, S, ST = ctypes.POINTER(af_mhd_params), ctypes.POINTER(af_mhd_state), ctypes.POINTER(af_mhd_stats_t)
+    vp = ctypes.c_void_p
+    L.af_mhd_workspace_bytes.argtypes = [P]
+    L.af_mhd_workspace_bytes.restype = ctypes.c_size_t
+    L.af_mhd_init.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.af_mhd_init.restype = ctypes.c_int
+    L.af_mhd_dt.argtypes = [vp, S, ctypes.c_double, vp]
+    L.af_mhd_dt.restype = ctypes.c_int
+    L.af_mhd_stage.argtypes = [vp, ctypes.c_int, S, S, S, vp]
+    L.af_mhd_stage.restype = ctypes.c_int
+    L.af_mhd_step.argtypes = [vp, S, ctypes.c_double, vp]
+    L.af_mhd_step.restype = ctypes.c_int
+    L.af_mhd_stats.argtypes = [vp, S, ST]
+    L.af_mhd_stats.restype = ctypes.c_int
+    L.af_mhd_reset_counters.argtypes = [vp]
+    L.af_mhd_reset_counters.restype = ctypes.c_int
+    L.af_mhd_destroy.argtypes = [vp]
+    L.af_mhd_destroy.restype = None
+    L.af_mhd_last_error.argtypes = [vp]
+    L.af_mhd_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_lib = load_library()
+
+
+class AfMhdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"af_mhd error {code}: {msg}")
+        self.code = code
+
+
+def make_params(prob) -> af_mhd_params:
+    """af_mhd_params from any object with nx, ny, x0, x1, y0, y1, gamma, cfl,
+    kappa, bc_x, bc_y attributes."""
+    return af_mhd_params(int(prob.nx), int(prob.ny), float(prob.x0), float(prob.x1), float(prob.y0),
+                         float(prob.y1), float(prob.gamma), float(prob.cfl), float(prob.kappa), int(prob.bc_x),
+                         int(prob.bc_y), 0)
+
+
+def af_mhd_workspace_bytes(params: af_mhd_params) -> int:
+    return int(_lib.af_mhd_workspace_bytes(ctypes.byref(params)))
+
+
+def _state(u) -> af_mhd_state:
+    for t in u:
+        if t.dtype.itemsize != 8 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("state arrays must be contiguous float64 device tensors")
+    return af_mhd_state(*[t.data_ptr() for t in u])
+
+
+class Context:
+    """Owns one af_mhd_ctx, its workspace and a device dt slot."""
+
+    def __init__(self, prob, device=None, stream=None):
+        import torch
+
+        self.prob = prob
+        self.params = make_params(prob)
+        nbytes = af_mhd_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise AfMhdError(AF_EINVAL, "invalid parameters")
+        self.device = torch.device(device if device is not None else "cuda")
+        # one extra 256-byte block so the workspace base can be aligned
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.dt_dev = torch.zeros(1, dtype=torch.float64, device=self.device)
+        h = ctypes.c_void_p()
+        rc = _lib.af_mhd_init(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr), nbytes,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != AF_OK:
+            raise AfMhdError(rc, "af_mhd_init failed")
+        self._h = h
+
+    def _check(self, rc: int, allow=(AF_OK,)):
+        if rc not in allow:
+            raise AfMhdError(rc, _lib.af_mhd_last_error(self._h).decode())
+        return rc
+
+    def af_mhd_dt(self, u, t_remaining: float = float("inf")):
+        self._check(_lib.af_mhd_dt(self._h, ctypes.byref(_state(u)), t_remaining,
+                                   ctypes.c_void_p(self.dt_dev.data_ptr())))
+        return self.dt_dev
+
+    def af_mhd_stage(self, k: int, un, uk, out, dt_dev=None):
+        dt_dev = self.dt_dev if dt_dev is None else dt_dev
+        self._check(_lib.af_mhd_stage(self._h, k, ctypes.byref(_state(un)), ctypes.byref(_state(uk)),
+                                      ctypes.byref(_state(out)), ctypes.c_void_p(dt_dev.data_ptr())))
+        return out
+
+    def af_mhd_step(self, u, t_remaining: float = float("inf")):
+        self._check(_lib.af_mhd_step(self._h, ctypes.byref(_state(u)), t_remaining,
+                                     ctypes.c_void_p(self.dt_dev.data_ptr())))
+        return u
+
+    def af_mhd_stats(self, u) -> dict:
+        st = af_mhd_stats_t()
+        rc = _lib.af_mhd_stats(self._h, ctypes.byref(_state(u)), ctypes.byref(st))
+        self._check(rc, allow=(AF_OK, AF_ENOTADMISSIBLE))
+        d = st.as_dict()
+        d["admissible"] = rc == AF_OK
+        return d
+
+    def af_mhd_reset_counters(self):
+        self._check(_lib.af_mhd_reset_counters(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.af_mhd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_device(state, device="cuda"):
+    import torch
+
+    return tuple(torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(device).contiguous()
+                 for a in state)
+
+
+def to_host(state):
+    return tuple(t.detach().cpu().numpy() for t in state)
+
+
+def empty_state(prob, device="cuda"):
+    import torch
+
+    return tuple(torch.empty(s, dtype=torch.float64, device=device) for s in prob.shapes())

@@ -1,0 +1,368 @@
+// af_device.h -- device-side building blocks of the Active Flux MHD stage
+// (gfx950).  Physics of Section 1 and eq. (cf), the LLF flux of eq.
+// (2d_llf_flux) with the Lemma's viscosity (Section 3.1), the limiters of
+// Sections 3.2-3.3, boundary index maps.  Included by the kernels only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace afm {
+
+constexpr int NV = 8;
+constexpr double EPS_FLOOR = 1e-13;   // lower bounds for rho and p (Sections 3.2, 3.3)
+constexpr double LAMBDA_REG = 1e-12;  // regulariser of the density box (Section 3.2)
+constexpr double SHRINK = 1e-8;       // round-off fallback step 2^m 1e-8, m = 0..9
+
+// Problem geometry, passed by value to every kernel.
+struct Geo {
+  int nx, ny, nxp, nyp, bcx, bcy;  // bc: 0 periodic, 1 outflow
+  double dx, dy, rdx, rdy, gamma, gm1, kappa, cfl;
+  long sc, sx, sy, sv;             // elements per component plane of each DoF set
+};
+
+struct CState {
+  const double* __restrict__ a;
+  const double* __restrict__ x;
+  const double* __restrict__ y;
+  const double* __restrict__ v;
+};
+struct MState {
+  double* __restrict__ a;
+  double* __restrict__ x;
+  double* __restrict__ y;
+  double* __restrict__ v;
+};
+
+// Device counters (integer atomics only; min_theta as the bit pattern of a
+// non-negative double, whose integer order is the numeric order).
+struct Counters {
+  unsigned long long n_llf_not_admissible, n_newton, newton_iters_max, n_fallback, n_not_admissible,
+      n_theta_active, n_point_limited, n_centre_limited, n_source_limited, min_theta_bits;
+};
+
+// --------------------------------------------------------------- boundaries
+// Periodic wrap, or outflow as an even mirror: cells mirror about the
+// boundary face, nodes about the boundary node.  |overshoot| <= n.
+__device__ __forceinline__ int map_cell(int i, int n, int bc) {
+  if (i < 0) return bc ? -1 - i : i + n;
+  if (i >= n) return bc ? 2 * n - 1 - i : i - n;
+  return i;
+}
+__device__ __forceinline__ int map_node(int k, int n, int bc) {
+  if (k < 0) return bc ? -k : k + n;
+  if (bc) return k > n ? 2 * n - k : k;
+  return k >= n ? k - n : k;
+}
+
+__device__ __forceinline__ void load8(const double* __restrict__ base, long plane, long off, double u[NV]) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) u[c] = base[c * plane + off];
+}
+__device__ __forceinline__ void ldA(const Geo& g, const double* a, int i, int j, double u[NV]) {
+  load8(a, g.sc, (long)map_cell(j, g.ny, g.bcy) * g.nx + map_cell(i, g.nx, g.bcx), u);
+}
+__device__ __forceinline__ void ldX(const Geo& g, const double* x, int k, int j, double u[NV]) {
+  load8(x, g.sx, (long)map_cell(j, g.ny, g.bcy) * g.nxp + map_node(k, g.nx, g.bcx), u);
+}
+__device__ __forceinline__ void ldY(const Geo& g, const double* y, int i, int l, double u[NV]) {
+  load8(y, g.sy, (long)map_node(l, g.ny, g.bcy) * g.nx + map_cell(i, g.nx, g.bcx), u);
+}
+__device__ __forceinline__ void ldV(const Geo& g, const double* v, int k, int l, double u[NV]) {
+  load8(v, g.sv, (long)map_node(l, g.ny, g.bcy) * g.nxp + map_node(k, g.nx, g.bcx), u);
+}
+
+// ------------------------------------------------------------------ physics
+// p = (gamma-1)(E - |m|^2/(2 rho) - |B|^2/2)
+__device__ __forceinline__ double pressure(const double U[NV], double gm1) {
+  const double m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+  const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+  return gm1 * (U[7] - 0.5 * m2 / U[0] - 0.5 * b2);
+}
+__device__ __forceinline__ bool in_G(const double U[NV], double gm1) {
+  return U[0] > 0.0 && pressure(U, gm1) > 0.0;
+}
+
+// What the directional stencils need from one state: the flux in the
+// direction, its spectral radius |v_n| + c_f, c_f, v_n and sqrt(rho).
+struct DirEval {
+  double F[NV];
+  double sr, cf, vn, sq;
+};
+
+// Flux F_n = v_n U + p_t (e_{m_n} + v_n e_E) - B_n (0, B, v, v.B): the
+// physical flux of Section 1 regrouped (transport, total pressure, tension).
+__device__ __forceinline__ void eval_dir(const double U[NV], const Geo& g, int dir, DirEval& e) {
+  const double ri = 1.0 / U[0];
+  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
+  const double B1 = U[4], B2 = U[5], B3 = U[6];
+  const double b2 = B1 * B1 + B2 * B2 + B3 * B3;
+  const double p = g.gm1 * (U[7] - 0.5 * (U[1] * v1 + U[2] * v2 + U[3] * v3) - 0.5 * b2);
+  const double pt = p + 0.5 * b2;
+  const double vB = v1 * B1 + v2 * B2 + v3 * B3;
+  const double vn = dir ? v2 : v1;
+  const double Bn = dir ? B2 : B1;
+  e.F[0] = U[0] * vn;
+  e.F[1] = vn * U[1] - Bn * B1 + (dir ? 0.0 : pt);
+  e.F[2] = vn * U[2] - Bn * B2 + (dir ? pt : 0.0);
+  e.F[3] = vn * U[3] - Bn * B3;
+  e.F[4] = dir ? (vn * B1 - Bn * v1) : 0.0;
+  e.F[5] = dir ? 0.0 : (vn * B2 - Bn * v2);
+  e.F[6] = vn * B3 - Bn * v3;
+  e.F[7] = (U[7] + pt) * vn - Bn * vB;
+  // fast magnetosonic speed, eq. (cf)
+  const double c2 = g.gamma * p * ri;
+  const double s = c2 + b2 * ri;
+  double disc = s * s - 4.0 * c2 * Bn * Bn * ri;
+  disc = disc > 0.0 ? disc : 0.0;
+  e.cf = sqrt(0.5 * (s + sqrt(disc)));
+  e.vn = vn;
+  e.sr = fabs(vn) + e.cf;
+  e.sq = sqrt(U[0]);
+}
+
+// Flux only (central differences and Simpson fluxes need no wave speed).
+__device__ __forceinline__ void flux_dir(const double U[NV], double gm1, int dir, double F[NV]) {
+  const double ri = 1.0 / U[0];
+  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
+  const double B1 = U[4], B2 = U[5], B3 = U[6];
+  const double b2 = B1 * B1 + B2 * B2 + B3 * B3;
+  const double p = gm1 * (U[7] - 0.5 * (U[1] * v1 + U[2] * v2 + U[3] * v3) - 0.5 * b2);
+  const double pt = p + 0.5 * b2;
+  const double vB = v1 * B1 + v2 * B2 + v3 * B3;
+  const double vn = dir ? v2 : v1;
+  const double Bn = dir ? B2 : B1;
+  F[0] = U[0] * vn;
+  F[1] = vn * U[1] - Bn * B1 + (dir ? 0.0 : pt);
+  F[2] = vn * U[2] - Bn * B2 + (dir ? pt : 0.0);
+  F[3] = vn * U[3] - Bn * B3;
+  F[4] = dir ? (vn * B1 - Bn * v1) : 0.0;
+  F[5] = dir ? 0.0 : (vn * B2 - Bn * v2);
+  F[6] = vn * B3 - Bn * v3;
+  F[7] = (U[7] + pt) * vn - Bn * vB;
+}
+
+// Godunov-Powell vector Psi = (0, B, v, v.B), eq. (gp_src).
+__device__ __forceinline__ void psi(const double U[NV], double P[NV]) {
+  const double ri = 1.0 / U[0];
+  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
+  P[0] = 0.0;
+  P[1] = U[4];
+  P[2] = U[5];
+  P[3] = U[6];
+  P[4] = v1;
+  P[5] = v2;
+  P[6] = v3;
+  P[7] = v1 * U[4] + v2 * U[5] + v3 * U[6];
+}
+
+// LLF viscosity of the Lemma, taken with equality: max of the two spectral
+// radii and of alpha_*(U,Ut), alpha_*(Ut,U); the latter two share all terms
+// but |v_n|, so their maximum uses max(|v_a|, |v_b|, |Roe-type average|).
+__device__ __forceinline__ double alpha_llf(const DirEval& a, const DirEval& b, const double Ua[NV],
+                                            const double Ub[NV]) {
+  const double inv = 1.0 / (a.sq + b.sq);
+  const double roe = fabs(a.sq * a.vn + b.sq * b.vn) * inv;
+  const double d1 = Ua[4] - Ub[4], d2 = Ua[5] - Ub[5], d3 = Ua[6] - Ub[6];
+  const double jump = sqrt(d1 * d1 + d2 * d2 + d3 * d3) * inv;
+  const double al = (fmax(fmax(fabs(a.vn), fabs(b.vn)), roe) + fmax(a.cf, b.cf)) + jump;
+  return fmax(al, fmax(a.sr, b.sr));
+}
+
+// -------------------------------------------------------------- counters
+__device__ __forceinline__ void count(unsigned long long* c) { atomicAdd(c, 1ull); }
+__device__ __forceinline__ void count_max(unsigned long long* c, unsigned long long v) { atomicMax(c, v); }
+__device__ __forceinline__ void count_min_theta(Counters* cn, double t) {
+  atomicMin(&cn->min_theta_bits, (unsigned long long)__double_as_longlong(t));
+}
+
+// ------------------------------------------------------------- limiters
+// Round-off fallback (closing remark of Section 4): when round-off leaves a
+// blended state outside G (rho > 0, p > 0), shrink its coefficient by
+// 2^m 1e-8 (m = 0..9, each from the original value); 0 if none passes.
+template <class Make>
+__device__ double shrink_into_G(double theta, double gm1, Make make, Counters* cn, bool counted) {
+  double W[NV];
+  for (int m = 0; m < 10; ++m) {
+    const double t = fmax(theta - ldexp(SHRINK, m), 0.0);
+    make(t, W);
+    if (in_G(W, gm1)) return t;
+  }
+  (void)cn;
+  (void)counted;
+  return 0.0;
+}
+
+// Scaling limiter of a point value (Section 3.3): density-only step, then a
+// whole-state blend towards the LLF state; eps from the LLF state.
+__device__ void limit_point(const double UH[NV], const double UL[NV], double gm1, double W[NV], Counters* cn) {
+  const double rhoL = UL[0], pL = pressure(UL, gm1);
+  const double er = fmin(EPS_FLOOR, rhoL), ep = fmin(EPS_FLOOR, pL);
+  double th1 = 1.0;
+  if (UH[0] < er) th1 = (rhoL - er) / (rhoL - UH[0]);
+  double Us[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Us[c] = UH[c];
+  if (th1 < 1.0) Us[0] = th1 * UH[0] + (1.0 - th1) * rhoL;
+  const double ps = pressure(Us, gm1);
+  double th2 = 1.0;
+  if (ps < ep) th2 = (pL - ep) / (pL - ps);
+  if (th1 < 1.0 || th2 < 1.0) count(&cn->n_point_limited);
+  auto make = [&](double t, double* Wt) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Wt[c] = t * Us[c] + (1.0 - t) * UL[c];
+  };
+  if (th2 == 1.0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) W[c] = Us[c];
+    // rho >= er and p >= ep already hold; both bounds are positive when the
+    // LLF state is in G, so W is in G without another evaluation.
+    if (rhoL > 0.0 && pL > 0.0 && Us[0] > 0.0) return;
+  } else {
+    make(th2, W);
+  }
+  if (th2 > 0.0 && !in_G(W, gm1)) {
+    count(&cn->n_fallback);
+    th2 = shrink_into_G(th2, gm1, make, cn, true);
+    make(th2, W);
+  }
+}
+
+// Limiter of the centre value (remark rmk:cell_center), reading: the whole
+// state is blended towards the cell average, first for rho >= eps_rho, then
+// for p >= eps_p, eps from the cell average.
+__device__ void limit_centre(const double Uc[NV], const double A[NV], double gm1, double C[NV], Counters* cn,
+                             bool counted) {
+  const double rhoA = A[0], pA = pressure(A, gm1);
+  const double er = fmin(EPS_FLOOR, rhoA), ep = fmin(EPS_FLOOR, pA);
+  double th1 = 1.0;
+  if (Uc[0] < er) th1 = (rhoA - er) / (rhoA - Uc[0]);
+  double Ur[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Ur[c] = th1 < 1.0 ? th1 * Uc[c] + (1.0 - th1) * A[c] : Uc[c];
+  const double pr = pressure(Ur, gm1);
+  double th2 = 1.0;
+  if (pr < ep) th2 = (pA - ep) / (pA - pr);
+  if (counted && (th1 < 1.0 || th2 < 1.0)) count(&cn->n_centre_limited);
+  auto make = [&](double t, double* Wt) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Wt[c] = t * Ur[c] + (1.0 - t) * A[c];
+  };
+  if (th2 == 1.0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) C[c] = Ur[c];
+    if (rhoA > 0.0 && pA > 0.0 && Ur[0] > 0.0) return;
+  } else {
+    make(th2, C);
+  }
+  if (th2 > 0.0 && !in_G(C, gm1)) {
+    if (counted) count(&cn->n_fallback);
+    th2 = shrink_into_G(th2, gm1, make, cn, counted);
+    make(th2, C);
+  }
+}
+
+// The pressure condition along A1 + r D as the cubic of Section 3.2,
+// q(r) = rho (E - |B|^2/2 - eps_p/(gamma-1)) - |m|^2/2, and dq/dr.
+__device__ __forceinline__ void pressure_cubic(const double A1[NV], const double D[NV], double r, double gm1,
+                                               double ep, double& q, double& dq) {
+  double W[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) W[c] = A1[c] + r * D[c];
+  const double b2 = W[4] * W[4] + W[5] * W[5] + W[6] * W[6];
+  const double m2 = W[1] * W[1] + W[2] * W[2] + W[3] * W[3];
+  const double e = W[7] - 0.5 * b2 - ep / gm1;
+  q = W[0] * e - 0.5 * m2;
+  const double de = D[7] - (W[4] * D[4] + W[5] * D[5] + W[6] * D[6]);
+  dq = D[0] * e + W[0] * de - (W[1] * D[1] + W[2] * D[2] + W[3] * D[3]);
+}
+
+// Root in (0,1) of the cubic by Newton from r = 1 inside a sign bracket.
+__device__ double vertex_root(const double A1[NV], const double D[NV], double gm1, double ep, int& iters) {
+  double lo = 0.0, hi = 1.0, r = 1.0;
+  iters = 0;
+  for (int it = 0; it < 50; ++it) {
+    double q, dq;
+    pressure_cubic(A1, D, r, gm1, ep, q, dq);
+    ++iters;
+    if (q >= 0.0) lo = r; else hi = r;
+    double rn = r - q / dq;
+    if (!(rn >= lo && rn <= hi)) rn = 0.5 * (lo + hi);
+    const double step = fabs(rn - r);
+    r = rn;
+    if (step <= 1e-13) break;
+  }
+  return r;
+}
+
+// Step (2) of the parametrized flux limiter (Section 3.2): density box,
+// pressure shrink over the 15 non-trivial vertices, Lambda_{L,R,D,U}, and
+// the round-off fallback on the final box.
+__device__ void limiter_box(const double A1[NV], const double H[4][NV], double gm1, double er, double ep,
+                            double Lam[4], Counters* cn, bool counted) {
+  double neg = 0.0;
+#pragma unroll
+  for (int I = 0; I < 4; ++I) neg += H[I][0] < 0.0 ? H[I][0] : 0.0;
+  double Lr[4];
+#pragma unroll
+  for (int I = 0; I < 4; ++I) Lr[I] = H[I][0] < 0.0 ? fmin(1.0, (A1[0] - er) / (LAMBDA_REG - neg)) : 1.0;
+  double rmin[4] = {1.0, 1.0, 1.0, 1.0};
+  bool any_root = false;
+  for (int k = 1; k < 16; ++k) {
+    double D[NV], W[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double d = 0.0;
+#pragma unroll
+      for (int I = 0; I < 4; ++I)
+        if (k & (1 << I)) d += Lr[I] * H[I][c];
+      D[c] = d;
+      W[c] = A1[c] + d;
+    }
+    if (pressure(W, gm1) < ep) {
+      int it;
+      const double r = vertex_root(A1, D, gm1, ep, it);
+      any_root = true;
+      if (counted) {
+        count(&cn->n_newton);
+        count_max(&cn->newton_iters_max, (unsigned long long)it);
+      }
+#pragma unroll
+      for (int I = 0; I < 4; ++I)
+        if (k & (1 << I)) rmin[I] = fmin(rmin[I], r);
+    }
+  }
+#pragma unroll
+  for (int I = 0; I < 4; ++I) Lam[I] = Lr[I] * rmin[I];
+  if (!any_root) return;
+  auto box_ok = [&](const double L[4]) {
+    for (int k = 1; k < 16; ++k) {
+      double W[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double d = 0.0;
+#pragma unroll
+        for (int I = 0; I < 4; ++I)
+          if (k & (1 << I)) d += L[I] * H[I][c];
+        W[c] = A1[c] + d;
+      }
+      if (!in_G(W, gm1)) return false;
+    }
+    return true;
+  };
+  if (box_ok(Lam)) return;
+  if (counted) count(&cn->n_fallback);
+  for (int m = 0; m < 10; ++m) {
+    double L[4];
+#pragma unroll
+    for (int I = 0; I < 4; ++I) L[I] = fmax(Lam[I] - ldexp(SHRINK, m), 0.0);
+    if (box_ok(L)) {
+#pragma unroll
+      for (int I = 0; I < 4; ++I) Lam[I] = L[I];
+      return;
+    }
+  }
+#pragma unroll
+  for (int I = 0; I < 4; ++I) Lam[I] = 0.0;
+}
+
+}  // namespace afm
