@@ -78,8 +78,20 @@ __device__ __forceinline__ double pressure(const double U[NV], double gm1) {
   const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
   return gm1 * (U[7] - 0.5 * m2 / U[0] - 0.5 * b2);
 }
+// rho p / (gamma-1) = rho E - |m|^2/2 - rho |B|^2/2: for rho > 0 it has the
+// sign of p and p >= eps  <=>  (gamma-1) * this >= rho * eps.  Decisions use
+// this division-free form; pressures are computed only where a limiter acts.
+__device__ __forceinline__ double rho_p(const double U[NV]) {
+  const double m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+  const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+  return U[0] * (U[7] - 0.5 * b2) - 0.5 * m2;
+}
 __device__ __forceinline__ bool in_G(const double U[NV], double gm1) {
-  return U[0] > 0.0 && pressure(U, gm1) > 0.0;
+  return U[0] > 0.0 && rho_p(U) > 0.0;
+}
+// p(U) >= eps for rho > 0
+__device__ __forceinline__ bool p_at_least(const double U[NV], double eps, double gm1) {
+  return gm1 * rho_p(U) >= U[0] * eps;
 }
 
 // What the directional stencils need from one state: the flux in the
@@ -180,23 +192,31 @@ __device__ __forceinline__ void count_min_theta(Counters* cn, double t) {
 // blended state outside G (rho > 0, p > 0), shrink its coefficient by
 // 2^m 1e-8 (m = 0..9, each from the original value); 0 if none passes.
 template <class Make>
-__device__ double shrink_into_G(double theta, double gm1, Make make, Counters* cn, bool counted) {
+__device__ double shrink_into_G(double theta, double gm1, Make make) {
   double W[NV];
   for (int m = 0; m < 10; ++m) {
     const double t = fmax(theta - ldexp(SHRINK, m), 0.0);
     make(t, W);
     if (in_G(W, gm1)) return t;
   }
-  (void)cn;
-  (void)counted;
   return 0.0;
 }
 
 // Scaling limiter of a point value (Section 3.3): density-only step, then a
 // whole-state blend towards the LLF state; eps from the LLF state.
-__device__ void limit_point(const double UH[NV], const double UL[NV], double gm1, double W[NV], Counters* cn) {
-  const double rhoL = UL[0], pL = pressure(UL, gm1);
-  const double er = fmin(EPS_FLOOR, rhoL), ep = fmin(EPS_FLOOR, pL);
+__device__ void limit_point(const double UH[NV], const double UL[NV], double gm1, double W[NV], Counters* cn,
+                            bool counted) {
+  const double rhoL = UL[0];
+  const double er = fmin(EPS_FLOOR, rhoL);
+  // common case: the LLF state has p >= 1e-13 (so eps_p = 1e-13) and the
+  // high-order state satisfies both bounds: no limiting, no division
+  if (rhoL > 0.0 && p_at_least(UL, EPS_FLOOR, gm1) && UH[0] >= er && p_at_least(UH, EPS_FLOOR, gm1)) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) W[c] = UH[c];
+    return;
+  }
+  const double pL = pressure(UL, gm1);
+  const double ep = fmin(EPS_FLOOR, pL);
   double th1 = 1.0;
   if (UH[0] < er) th1 = (rhoL - er) / (rhoL - UH[0]);
   double Us[NV];
@@ -206,7 +226,7 @@ __device__ void limit_point(const double UH[NV], const double UL[NV], double gm1
   const double ps = pressure(Us, gm1);
   double th2 = 1.0;
   if (ps < ep) th2 = (pL - ep) / (pL - ps);
-  if (th1 < 1.0 || th2 < 1.0) count(&cn->n_point_limited);
+  if (counted && (th1 < 1.0 || th2 < 1.0)) count(&cn->n_point_limited);
   auto make = [&](double t, double* Wt) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) Wt[c] = t * Us[c] + (1.0 - t) * UL[c];
@@ -221,8 +241,8 @@ __device__ void limit_point(const double UH[NV], const double UL[NV], double gm1
     make(th2, W);
   }
   if (th2 > 0.0 && !in_G(W, gm1)) {
-    count(&cn->n_fallback);
-    th2 = shrink_into_G(th2, gm1, make, cn, true);
+    if (counted) count(&cn->n_fallback);
+    th2 = shrink_into_G(th2, gm1, make);
     make(th2, W);
   }
 }
@@ -232,8 +252,15 @@ __device__ void limit_point(const double UH[NV], const double UL[NV], double gm1
 // for p >= eps_p, eps from the cell average.
 __device__ void limit_centre(const double Uc[NV], const double A[NV], double gm1, double C[NV], Counters* cn,
                              bool counted) {
-  const double rhoA = A[0], pA = pressure(A, gm1);
-  const double er = fmin(EPS_FLOOR, rhoA), ep = fmin(EPS_FLOOR, pA);
+  const double rhoA = A[0];
+  const double er = fmin(EPS_FLOOR, rhoA);
+  if (rhoA > 0.0 && p_at_least(A, EPS_FLOOR, gm1) && Uc[0] >= er && p_at_least(Uc, EPS_FLOOR, gm1)) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) C[c] = Uc[c];
+    return;
+  }
+  const double pA = pressure(A, gm1);
+  const double ep = fmin(EPS_FLOOR, pA);
   double th1 = 1.0;
   if (Uc[0] < er) th1 = (rhoA - er) / (rhoA - Uc[0]);
   double Ur[NV];
@@ -256,7 +283,7 @@ __device__ void limit_centre(const double Uc[NV], const double A[NV], double gm1
   }
   if (th2 > 0.0 && !in_G(C, gm1)) {
     if (counted) count(&cn->n_fallback);
-    th2 = shrink_into_G(th2, gm1, make, cn, counted);
+    th2 = shrink_into_G(th2, gm1, make);
     make(th2, C);
   }
 }
@@ -305,6 +332,25 @@ __device__ void limiter_box(const double A1[NV], const double H[4][NV], double g
   double Lr[4];
 #pragma unroll
   for (int I = 0; I < 4; ++I) Lr[I] = H[I][0] < 0.0 ? fmin(1.0, (A1[0] - er) / (LAMBDA_REG - neg)) : 1.0;
+  // Sufficient test: every vertex A1 + sum_{I in K} Lr_I H_I is a convex
+  // combination of A1 and the four points A1 + 4 Lr_I H_I (weights 1/4 and
+  // 1 - |K|/4), and {rho >= er, p >= ep} is convex; when those four points
+  // are admissible no vertex needs the pressure shrink.
+  {
+    bool all_ok = true;
+#pragma unroll
+    for (int I = 0; I < 4; ++I) {
+      double W[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) W[c] = A1[c] + 4.0 * (Lr[I] * H[I][c]);
+      all_ok = all_ok && W[0] >= er && W[0] > 0.0 && p_at_least(W, ep, gm1);
+    }
+    if (all_ok) {
+#pragma unroll
+      for (int I = 0; I < 4; ++I) Lam[I] = Lr[I];
+      return;
+    }
+  }
   double rmin[4] = {1.0, 1.0, 1.0, 1.0};
   bool any_root = false;
   for (int k = 1; k < 16; ++k) {

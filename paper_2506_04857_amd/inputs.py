@@ -254,14 +254,17 @@ def random_smooth(n: int = 16, ny: int | None = None, seed: int = BASE_SEED, amp
 
 
 def random_shock(n: int = 16, ny: int | None = None, seed: int = BASE_SEED, bc: int = OUTFLOW,
-                 field_jump: float = 0.0) -> Problem:
+                 field_jump: float = 0.0, centre: tuple | None = None) -> Problem:
     """Seeded random piecewise-constant states with a strong pressure and
     density jump across a random circle (limiter-active parity cases).  With
     field_jump > 0 the magnetic field also jumps across the circle, which
-    makes div B nonzero there."""
+    makes div B nonzero there.  ``centre`` (in units of the x extent) places
+    the circle, e.g. on a boundary so that the jump crosses it."""
     rng = np.random.default_rng(seed)
     ny = n if ny is None else ny
     cx, cy = rng.uniform(0.35, 0.65, size=2)
+    if centre is not None:
+        cx, cy = centre
     r0 = rng.uniform(0.15, 0.3)
     inner = np.array([1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0]) + rng.uniform(-0.2, 0.2, size=8)
     inner[0], inner[7] = 1.0, 1000.0

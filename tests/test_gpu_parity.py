@@ -73,6 +73,14 @@ SINGLE = [
     ("shock_18x15_periodic_k0", lambda: replace(I.random_shock(18, 15, seed=1, bc=I.PERIODIC, field_jump=3.0),
                                                 kappa=0.0)),
     ("orszag_tang_70x37", lambda: I.orszag_tang(70).with_size(70, 37)),
+    # jumps that cross the boundaries: limiter and sensor active in the
+    # boundary cells and their ghost neighbours
+    ("shock_edge_16x13_outflow", lambda: I.random_shock(16, 13, seed=7, bc=I.OUTFLOW, field_jump=3.0,
+                                                        centre=(0.97, 0.5))),
+    ("shock_corner_16x13_periodic", lambda: I.random_shock(16, 13, seed=9, bc=I.PERIODIC, field_jump=3.0,
+                                                           centre=(0.98, 0.03))),
+    ("shock_corner_40x23_outflow", lambda: I.random_shock(40, 23, seed=3, bc=I.OUTFLOW, field_jump=3.0,
+                                                          centre=(0.02, 0.05))),
 ]
 
 
