@@ -5,8 +5,13 @@ timed region).
 
 python bench.py [--steps K] [--warmup W] [--workload orszag_tang_512|blast_lowbeta_1024|alfven_32]
 Prints one JSON line.
+
+python bench.py --copy-calibration MIB
+runs a plain device-to-device copy of MIB MiB three times (the known-size
+kernel against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled) and exits.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -16,10 +21,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "cell-updates/s per RK stage (FP64 vs FP32-bulk), %HBM peak; adjoint/fwd time"
+UNIT = "cell-updates/s per RK stage"
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per cell per stage (FP64 storage, 4 DoF sets x 8 variables):
-# read U^n and U^(k) (256 B each; one array at k = 0), write U^(k+1) (256 B)
+
+# Algorithmic HBM bytes per cell (FP64 storage; 4 DoF sets x 8 variables,
+# 64 B per set), averaged over the three stages (a_k = 0 at k = 0, so U^n
+# is not read there):
+#   whole stage: read U^(k) 256, read U^n 256 (k >= 1), write 256
 BYTES_PER_CELL_STAGE = (512 + 768 + 768) / 3.0
+#   cell-average kernel: read U^(k) (all four sets) 256, read A^n 64 (k >= 1),
+#   write A 64
+BYTES_PER_CELL_CELLS = 256 + 64 * 2.0 / 3.0 + 64
+#   point kernel: read U^(k) 256, read X^n, Y^n, V^n 192 (k >= 1), write 192
+BYTES_PER_CELL_POINTS = 256 + 192 * 2.0 / 3.0 + 192
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cells_orszag_tang_512_traffic.txt")
+
+
+def source_hash() -> str:
+    """SHA-256 over the HIP sources and headers the library is built from."""
+    h = hashlib.sha256()
+    for d in (os.path.join(ROOT, "paper_2506_04857_amd", "csrc"), os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".h")):
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per k_cells launch from the committed rocprofv3 counter
+    summary, or None when it is missing, for another workload, or taken
+    from a different kernel source."""
+    if workload != "orszag_tang_512" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(prob, u0, budget_s=12.0):
@@ -29,17 +77,40 @@ def cpu_baseline(prob, u0, budget_s=12.0):
     dt = orc.dt(prob, u0, nthreads=threads)
     t0 = time.perf_counter()
     n = 0
-    u = u0
     while True:
-        u = orc.stage(prob, 0, u0, u0, dt, nthreads=threads)
+        orc.stage(prob, 0, u0, u0, dt, nthreads=threads)
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": prob.nx * prob.ny * n / el, "unit": "cell-updates/s per RK stage", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n} forward-Euler stages of {prob.name} {prob.nx}x{prob.ny} from the initial data, "
-                      f"{el:.1f} s, FP64 C++ oracle with OpenMP"}
+    return {"value": prob.nx * prob.ny * n / el, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"{n} forward-Euler stages of {prob.name} {prob.nx}x{prob.ny} from the initial data "
+                      f"in {el:.1f} s (FP64 C++ oracle, OpenMP over rows)"}
+
+
+def copy_calibration(mib: int):
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "launches": 3}))
+
+
+def timed_steps(ctx, u, steps, stream):
+    import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        ctx.af_mhd_step(u)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1)
 
 
 def main():
@@ -49,42 +120,56 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="orszag_tang_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this implementation runs on one GPU; multi-GPU runs are not supported "
+                                   "(--gpus must be 1)"}))
         sys.exit(2)
-
-    import torch
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     from paper_2506_04857_amd import af_mhd as af
     from paper_2506_04857_amd import inputs as I
 
     prob = I.CONFIGS[args.workload]()
     u0 = I.sample(prob)
-    ctx = af.Context(prob)
-    u = af.to_device(u0)
-    stream = ctx.stream
-    for _ in range(args.warmup):
-        ctx.af_mhd_step(u)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        ctx.af_mhd_step(u)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    st = ctx.af_mhd_stats(u)
     cells = prob.nx * prob.ny
     stages = 3 * args.steps
+
+    # timed region: K whole steps (dt reduction + three stages), no timing events
+    ctx = af.Context(prob)
+    u = af.to_device(u0)
+    for _ in range(args.warmup):
+        ctx.af_mhd_step(u)
+    ms = timed_steps(ctx, u, args.steps, ctx.stream)
+    st = ctx.af_mhd_stats(u)
+    ctx.close()
     t_stage = ms * 1e-3 / stages
     value = cells / t_stage
-    achieved = BYTES_PER_CELL_STAGE * cells / t_stage / 1e9
+
+    # second pass with per-kernel HIP events on the launch stream: the
+    # dominant kernel's average launch duration for the roofline
+    tctx = af.Context(prob, flags=af.AF_FLAG_KERNEL_TIMING)
+    u = af.to_device(u0)
+    for _ in range(args.warmup):
+        tctx.af_mhd_step(u)
+    tctx.af_mhd_kernel_times(reset=True)
+    timed_steps(tctx, u, args.steps, tctx.stream)
+    kt = tctx.af_mhd_kernel_times()
+    tctx.close()
+    us_cells = 1e3 * kt["ms_cells"] / max(kt["n_cells"], 1)
+    us_points = 1e3 * kt["ms_points"] / max(kt["n_points"], 1)
+    us_dt = 1e3 * kt["ms_dt"] / max(kt["n_dt"], 1)
+    algo_cells = BYTES_PER_CELL_CELLS * cells
+    achieved = algo_cells / (us_cells * 1e-6) / 1e9
+    traffic = measured_traffic(args.workload)
+
     out = {
-        "metric": "cell-updates/s per RK stage (FP64), %HBM peak",
+        "metric": METRIC,
         "value": value,
-        "unit": "cell-updates/s per RK stage",
+        "unit": UNIT,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -95,14 +180,17 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{prob.name} {prob.nx}x{prob.ny}", "nx": prob.nx, "ny": prob.ny,
-                   "cells": cells, "precision": "fp64", "cfl": prob.cfl, "kappa": prob.kappa},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                   "cells": cells, "cfl": prob.cfl, "kappa": prob.kappa,
+                   "boundary": "periodic" if prob.bc_x == 0 else "outflow"},
+        "roofline": {"bound": "hbm", "kernel": "k_cells", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": algo_cells, "avg_launch_us": us_cells},
+        "kernels_us": {"k_cells": us_cells, "k_points": us_points, "dt": us_dt},
+        "stage_hbm_gbs": BYTES_PER_CELL_STAGE * cells / t_stage / 1e9,
         "admissible": bool(st["admissible"]),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, u0)
-    ctx.close()
     print(json.dumps(out))
 
 

@@ -61,8 +61,20 @@ typedef struct {
   double cfl;               /* dt = cfl / max over all DoFs of (rho_1/dx + rho_2/dy), in (0,1] */
   double kappa;             /* shock-sensor strength (Section 3.4), >= 0; 0 disables the sensor */
   int32_t bc_x, bc_y;       /* AF_BC_PERIODIC or AF_BC_OUTFLOW per direction */
-  uint32_t flags;           /* must be 0 */
+  uint32_t flags;           /* 0 or AF_FLAG_KERNEL_TIMING; other bits are rejected */
 } af_mhd_params;
+
+/* Record HIP events on the context's stream around every kernel launch so
+ * that af_mhd_kernel_times can report per-kernel device time.  Costs one
+ * event record per launch boundary; off by default. */
+#define AF_FLAG_KERNEL_TIMING 4u
+
+typedef struct {            /* device time since init or the last reset */
+  double ms_points;         /* point-value kernel (V, X, Y update) */
+  double ms_cells;          /* cell-average kernel */
+  double ms_dt;             /* time-step reduction */
+  int64_t n_points, n_cells, n_dt;  /* launches timed */
+} af_mhd_kernel_times_t;
 
 typedef struct {            /* one state: the four DoF sets (layout above) */
   double* cell;
@@ -125,9 +137,16 @@ int af_mhd_stats(af_mhd_ctx* c, const af_mhd_state* u, af_mhd_stats_t* out);
 /* Reset the counters to zero (asynchronously on the stream). */
 int af_mhd_reset_counters(af_mhd_ctx* c);
 
+/* Per-kernel device time of a context created with AF_FLAG_KERNEL_TIMING
+ * (AF_EINVAL otherwise).  Synchronises the stream.  reset != 0 zeroes the
+ * totals after reading them.  Not a step of the method: a measurement aid. */
+int af_mhd_kernel_times(af_mhd_ctx* c, af_mhd_kernel_times_t* out, int reset);
+
 void af_mhd_destroy(af_mhd_ctx* c);
 
-/* Message of the last error on this context ("" if none); valid until the next call. */
+/* Message of the last error on this context ("" if none); valid until the
+ * next call.  With c == NULL: the message of this thread's last failed
+ * af_mhd_init. */
 const char* af_mhd_last_error(const af_mhd_ctx* c);
 
 #ifdef __cplusplus

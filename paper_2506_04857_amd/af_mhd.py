@@ -50,7 +50,25 @@ class af_mhd_stats_t(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+AF_FLAG_KERNEL_TIMING = 4
+
+
+class af_mhd_kernel_times_t(ctypes.Structure):
+    _fields_ = [
+        ("ms_points", ctypes.c_double), ("ms_cells", ctypes.c_double), ("ms_dt", ctypes.c_double),
+        ("n_points", ctypes.c_int64), ("n_cells", ctypes.c_int64), ("n_dt", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    # torch first: the process must hold one HIP runtime, and torch brings
+    # its own copy of libamdhip64; loading the library first would bind it to
+    # the system copy and make torch's streams and memory foreign to it.
+    import torch  # noqa: F401
+
     if not os.path.exists(path):
         raise ImportError(f"HIP library {path} is not built; run __graft_entry__.build() "
                           "or python -m paper_2506_04857_amd.build")
@@ -71,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.af_mhd_stats.restype = ctypes.c_int
     L.af_mhd_reset_counters.argtypes = [vp]
     L.af_mhd_reset_counters.restype = ctypes.c_int
+    L.af_mhd_kernel_times.argtypes = [vp, ctypes.POINTER(af_mhd_kernel_times_t), ctypes.c_int]
+    L.af_mhd_kernel_times.restype = ctypes.c_int
     L.af_mhd_destroy.argtypes = [vp]
     L.af_mhd_destroy.restype = None
     L.af_mhd_last_error.argtypes = [vp]
@@ -87,12 +107,12 @@ class AfMhdError(RuntimeError):
         self.code = code
 
 
-def make_params(prob) -> af_mhd_params:
+def make_params(prob, flags: int = 0) -> af_mhd_params:
     """af_mhd_params from any object with nx, ny, x0, x1, y0, y1, gamma, cfl,
     kappa, bc_x, bc_y attributes."""
     return af_mhd_params(int(prob.nx), int(prob.ny), float(prob.x0), float(prob.x1), float(prob.y0),
                          float(prob.y1), float(prob.gamma), float(prob.cfl), float(prob.kappa), int(prob.bc_x),
-                         int(prob.bc_y), 0)
+                         int(prob.bc_y), int(flags))
 
 
 def af_mhd_workspace_bytes(params: af_mhd_params) -> int:
@@ -109,11 +129,11 @@ def _state(u) -> af_mhd_state:
 class Context:
     """Owns one af_mhd_ctx, its workspace and a device dt slot."""
 
-    def __init__(self, prob, device=None, stream=None):
+    def __init__(self, prob, device=None, stream=None, flags: int = 0):
         import torch
 
         self.prob = prob
-        self.params = make_params(prob)
+        self.params = make_params(prob, flags)
         nbytes = af_mhd_workspace_bytes(self.params)
         if nbytes == 0:
             raise AfMhdError(AF_EINVAL, "invalid parameters")
@@ -128,7 +148,7 @@ class Context:
         rc = _lib.af_mhd_init(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr), nbytes,
                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if rc != AF_OK:
-            raise AfMhdError(rc, "af_mhd_init failed")
+            raise AfMhdError(rc, "af_mhd_init failed: " + _lib.af_mhd_last_error(None).decode())
         self._h = h
 
     def _check(self, rc: int, allow=(AF_OK,)):
@@ -162,6 +182,11 @@ class Context:
 
     def af_mhd_reset_counters(self):
         self._check(_lib.af_mhd_reset_counters(self._h))
+
+    def af_mhd_kernel_times(self, reset: bool = False) -> dict:
+        kt = af_mhd_kernel_times_t()
+        self._check(_lib.af_mhd_kernel_times(self._h, ctypes.byref(kt), int(bool(reset))))
+        return kt.as_dict()
 
     def close(self):
         if getattr(self, "_h", None):

@@ -323,15 +323,20 @@ __device__ double vertex_root(const double A1[NV], const double D[NV], double gm
 
 // Step (2) of the parametrized flux limiter (Section 3.2): density box,
 // pressure shrink over the 15 non-trivial vertices, Lambda_{L,R,D,U}, and
-// the round-off fallback on the final box.
-__device__ void limiter_box(const double A1[NV], const double H[4][NV], double gm1, double er, double ep,
-                            double Lam[4], Counters* cn, bool counted) {
+// the round-off fallback on the final box.  H(I, c) returns component c of
+// the anti-diffusive update H_I (I = L, R, D, U).
+template <class HF>
+__device__ void limiter_box(const double A1[NV], HF H, double gm1, double er, double ep, double Lam[4], Counters* cn,
+                            bool counted) {
+  double h0[4];
+#pragma unroll
+  for (int I = 0; I < 4; ++I) h0[I] = H(I, 0);
   double neg = 0.0;
 #pragma unroll
-  for (int I = 0; I < 4; ++I) neg += H[I][0] < 0.0 ? H[I][0] : 0.0;
+  for (int I = 0; I < 4; ++I) neg += h0[I] < 0.0 ? h0[I] : 0.0;
   double Lr[4];
 #pragma unroll
-  for (int I = 0; I < 4; ++I) Lr[I] = H[I][0] < 0.0 ? fmin(1.0, (A1[0] - er) / (LAMBDA_REG - neg)) : 1.0;
+  for (int I = 0; I < 4; ++I) Lr[I] = h0[I] < 0.0 ? fmin(1.0, (A1[0] - er) / (LAMBDA_REG - neg)) : 1.0;
   // Sufficient test: every vertex A1 + sum_{I in K} Lr_I H_I is a convex
   // combination of A1 and the four points A1 + 4 Lr_I H_I (weights 1/4 and
   // 1 - |K|/4), and {rho >= er, p >= ep} is convex; when those four points
@@ -342,7 +347,7 @@ __device__ void limiter_box(const double A1[NV], const double H[4][NV], double g
     for (int I = 0; I < 4; ++I) {
       double W[NV];
 #pragma unroll
-      for (int c = 0; c < NV; ++c) W[c] = A1[c] + 4.0 * (Lr[I] * H[I][c]);
+      for (int c = 0; c < NV; ++c) W[c] = A1[c] + 4.0 * (Lr[I] * H(I, c));
       all_ok = all_ok && W[0] >= er && W[0] > 0.0 && p_at_least(W, ep, gm1);
     }
     if (all_ok) {
@@ -360,7 +365,7 @@ __device__ void limiter_box(const double A1[NV], const double H[4][NV], double g
       double d = 0.0;
 #pragma unroll
       for (int I = 0; I < 4; ++I)
-        if (k & (1 << I)) d += Lr[I] * H[I][c];
+        if (k & (1 << I)) d += Lr[I] * H(I, c);
       D[c] = d;
       W[c] = A1[c] + d;
     }
@@ -388,7 +393,7 @@ __device__ void limiter_box(const double A1[NV], const double H[4][NV], double g
         double d = 0.0;
 #pragma unroll
         for (int I = 0; I < 4; ++I)
-          if (k & (1 << I)) d += L[I] * H[I][c];
+          if (k & (1 << I)) d += L[I] * H(I, c);
         W[c] = A1[c] + d;
       }
       if (!in_G(W, gm1)) return false;

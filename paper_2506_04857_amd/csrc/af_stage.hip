@@ -33,49 +33,25 @@ struct WS {                 // workspace pointers
   double* partial;          // reduction partials
   Counters* cnt;
   double* scratch[2][4];    // two RK scratch states
+  double* centre;           // limited centre values of the stage input, [8][ny][nx]
 };
 
-// Centre value of cell (i,j) from the bi-parabolic reconstruction
-// (Section 2.1): C = [36 A - 4 (face values) - (vertex values)] / 16, then
-// limited towards A (remark rmk:cell_center).  Also returns the nine sample
-// points of the cell through the callback keep(a, b, U) (a along x, b along y).
-template <class Keep>
-__device__ __forceinline__ void centre_and_points(const Geo& g, CState u, int i, int j, const double A[NV],
-                                                  double C[NV], Counters* cn, bool counted, Keep keep) {
-  double w[NV], Uc[NV], f[NV];
-  ldX(g, u.x, i, j, w);
-  keep(0, 1, w);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) f[q] = w[q];
-  ldX(g, u.x, i + 1, j, w);
-  keep(2, 1, w);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) f[q] += w[q];
-  ldY(g, u.y, i, j, w);
-  keep(1, 0, w);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) Uc[q] = w[q];
-  ldY(g, u.y, i, j + 1, w);
-  keep(1, 2, w);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) f[q] = -4.0 * (f[q] + (Uc[q] + w[q]));
-  ldV(g, u.v, i, j, w);
-  keep(0, 0, w);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) Uc[q] = w[q];
-  ldV(g, u.v, i + 1, j, w);
-  keep(2, 0, w);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) Uc[q] += w[q];
-  double v2[NV];
-  ldV(g, u.v, i, j + 1, v2);
-  keep(0, 2, v2);
-  ldV(g, u.v, i + 1, j + 1, w);
-  keep(2, 2, w);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) Uc[q] = (36.0 * A[q] + f[q] - (Uc[q] + (v2[q] + w[q]))) * 0.0625;
-  limit_centre(Uc, A, g.gm1, C, cn, counted);
+// XCD-aware tile order: the hardware deals consecutive workgroups round-robin
+// to the 8 XCDs, each with its own L2.  Workgroup b takes logical tile
+// (b % 8) * per + b / 8, so every XCD walks one contiguous band of tiles in
+// row-major order and the halos its tiles share stay in its L2.  Returns
+// false for the padding workgroups of the last band.
+constexpr int NXCD = 8;
+__device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& bx, int& by) {
+  const int n = ntx * nty, per = (n + NXCD - 1) / NXCD;
+  const int b = (int)blockIdx.x;
+  const int t = (b % NXCD) * per + b / NXCD;
+  if (t >= n) return false;
+  bx = t % ntx;
+  by = t / ntx;
+  return true;
 }
+inline int xcd_grid(int ntx, int nty) { return NXCD * ((ntx * nty + NXCD - 1) / NXCD); }
 
 __device__ double sensor_pressure(const double U[NV], double gamma) {
 #pragma clang fp contract(off)
@@ -104,6 +80,25 @@ __device__ double sensor_pressure(const double U[NV], double gamma) {
 // line neighbours at +-h for FVS directions, at +-h/2 for the central one).
 constexpr int PB = 16, PNT = PB * PB;
 constexpr int RF = 12;  // record: F[8], sr, cf, vn, sq
+
+template <int W, int H>
+__device__ __forceinline__ void put_rec(double (*s)[H][W], int ty, int tx, const DirEval& e) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) s[c][ty][tx] = e.F[c];
+  s[8][ty][tx] = e.sr;
+  s[9][ty][tx] = e.cf;
+  s[10][ty][tx] = e.vn;
+  s[11][ty][tx] = e.sq;
+}
+template <int W, int H>
+__device__ __forceinline__ void get_rec(double (*s)[H][W], int ty, int tx, DirEval& e) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) e.F[c] = s[c][ty][tx];
+  e.sr = s[8][ty][tx];
+  e.cf = s[9][ty][tx];
+  e.vn = s[10][ty][tx];
+  e.sq = s[11][ty][tx];
+}
 
 __device__ __forceinline__ void put_rec(double (*s)[PB][PB], int base, int ty, int tx, const DirEval& e) {
 #pragma unroll
@@ -244,11 +239,14 @@ __device__ __forceinline__ void lds8(double (*s)[PB][PB], int base, int ty, int 
   for (int c = 0; c < NV; ++c) U[c] = s[base + c][ty][tx];
 }
 
-__global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MState out, const double* dtp, double ca,
-                                                double cb, Counters* cn) {
+__global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MState out, double* __restrict__ centre,
+                                                const double* dtp, double ca, double cb, Counters* cn, int ntx,
+                                                int nty) {
   __shared__ double s[SFIELDS][PB][PB];
+  int bx, by;
+  if (!xcd_tile(ntx, nty, bx, by)) return;
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int i0 = (int)blockIdx.x * (PB - 2) - 1, j0 = (int)blockIdx.y * (PB - 2) - 1;
+  const int i0 = bx * (PB - 2) - 1, j0 = by * (PB - 2) - 1;
   const int i = clamp_pt(i0 + tx, g.nxp), j = clamp_pt(j0 + ty, g.nyp);
   const bool inner = tx >= 1 && tx < PB - 1 && ty >= 1 && ty < PB - 1;
   const bool outV = inner && i0 + tx < g.nxp && j0 + ty < g.nyp;
@@ -291,9 +289,14 @@ __global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MSta
     lds8(s, SV_, tyu, txr, w);
 #pragma unroll
     for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
-    limit_centre(Uc, A, g.gm1, C, cn, inner && i0 + tx < g.nx && j0 + ty < g.ny);
+    const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
+    limit_centre(Uc, A, g.gm1, C, cn, owner);
 #pragma unroll
     for (int c = 0; c < NV; ++c) s[SC_ + c][ty][tx] = C[c];
+    if (owner) {  // for the cell kernel's source term
+#pragma unroll
+      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C[c];
+    }
   }
   PointAcc PA, PB_;
   DirEval e0, e1, en;
@@ -443,18 +446,39 @@ __device__ void sensor_from_prims(const double c[5], const double l[5], const do
 // Nine-point Powell source of cell (i,j), eq. (semi_av_src): weights
 // (1/6, 2/3, 1/6) per direction, the divergence at each sample point from
 // the one-sided / central differences of eq. (2d_fd) along the cell's rows
-// and columns, Psi at each point; the centre value is the limited one.
-__device__ void cell_source(const Geo& g, CState u, int i, int j, const double A[NV], double S[NV]) {
-  double B1[3][3], B2[3][3], C[NV];  // [a][b]: a along x, b along y
-  centre_and_points(g, u, i, j, A, C, nullptr, false, [&](int a, int b, const double* w) {
-    B1[a][b] = w[4];
-    B2[a][b] = w[5];
-  });
-  B1[1][1] = C[4];
-  B2[1][1] = C[5];
-  const double wq[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+// and columns, Psi at each point.  The centre sample is the limited centre
+// value, read from the buffer the point kernel fills.
+__device__ void cell_source(const Geo& g, CState u, const double* __restrict__ centre, int i, int j,
+                            double S[NV]) {
+  double C[NV];
+  ldA(g, centre, i, j, C);
+  // B1, B2 at the nine samples, [a][b] with a along x, b along y
+  double B1[3][3], B2[3][3];
+  auto ldB = [&](int a, int b, double& b1, double& b2) {
+    long off;
+    const double* base;
+    long plane;
+    if (a == 1 && b == 1) {
+      b1 = C[4];
+      b2 = C[5];
+      return;
+    } else if (b == 1) {
+      base = u.x, plane = g.sx, off = (long)map_cell(j, g.ny, g.bcy) * g.nxp + map_node(i + a / 2, g.nx, g.bcx);
+    } else if (a == 1) {
+      base = u.y, plane = g.sy, off = (long)map_node(j + b / 2, g.ny, g.bcy) * g.nx + map_cell(i, g.nx, g.bcx);
+    } else {
+      base = u.v, plane = g.sv,
+      off = (long)map_node(j + b / 2, g.ny, g.bcy) * g.nxp + map_node(i + a / 2, g.nx, g.bcx);
+    }
+    b1 = base[4 * plane + off];
+    b2 = base[5 * plane + off];
+  };
 #pragma unroll
-  for (int c = 0; c < NV; ++c) S[c] = 0.0;
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ldB(a, b, B1[a][b], B2[a][b]);
+  const double wq[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+  double f[9];
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
@@ -465,22 +489,33 @@ __device__ void cell_source(const Geo& g, CState u, int i, int j, const double A
       const double dy2 = b == 0 ? (-3.0 * B2[a][0] + 4.0 * B2[a][1] - B2[a][2])
                        : b == 1 ? (B2[a][2] - B2[a][0])
                                 : (B2[a][0] - 4.0 * B2[a][1] + 3.0 * B2[a][2]);
-      const double f = wq[a] * wq[b] * (dx1 * g.rdx + dy2 * g.rdy);
-      double w[NV], P[NV];
-      if (a == 1 && b == 1) {
-#pragma unroll
-        for (int c = 0; c < NV; ++c) w[c] = C[c];
-      } else if (b == 1) {
-        ldX(g, u.x, i + a / 2, j, w);
-      } else if (a == 1) {
-        ldY(g, u.y, i, j + b / 2, w);
-      } else {
-        ldV(g, u.v, i + a / 2, j + b / 2, w);
-      }
-      psi(w, P);
-#pragma unroll
-      for (int c = 1; c < NV; ++c) S[c] += f * P[c];
+      f[3 * b + a] = wq[a] * wq[b] * (dx1 * g.rdx + dy2 * g.rdy);
     }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) S[c] = 0.0;
+  // One sample at a time (a rolled loop): the states of all nine are never
+  // live together.
+#pragma unroll 1
+  for (int q = 0; q < 9; ++q) {
+    const int a = q % 3, b = q / 3;
+    double fq = f[0];
+#pragma unroll
+    for (int r = 1; r < 9; ++r) fq = q == r ? f[r] : fq;
+    double w[NV], P[NV];
+    if (q == 4) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) w[c] = C[c];
+    } else if (b == 1) {
+      ldX(g, u.x, i + a / 2, j, w);
+    } else if (a == 1) {
+      ldY(g, u.y, i, j + b / 2, w);
+    } else {
+      ldV(g, u.v, i + a / 2, j + b / 2, w);
+    }
+    psi(w, P);
+#pragma unroll
+    for (int c = 1; c < NV; ++c) S[c] += fq * P[c];
+  }
 }
 
 __device__ __forceinline__ int clamp_cell(int i, int n) { return i < -2 ? -2 : (i > n + 1 ? n + 1 : i); }
@@ -488,27 +523,6 @@ __device__ __forceinline__ int clamp_cell(int i, int n) { return i < -2 ? -2 : (
 // ghost cells -2 and n+1 enter the sensor of the outermost interfaces whose
 // flux-limiter coefficients the boundary cells take.
 __device__ __forceinline__ int clamp_prim(int i, int n) { return i < -3 ? -3 : (i > n + 2 ? n + 2 : i); }
-
-__device__ __forceinline__ void put_xrec(double (*s)[CBY][CBX], int ty, int tx, const DirEval& e, const double U[NV]) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) s[c][ty][tx] = e.F[c];
-  s[8][ty][tx] = e.sr;
-  s[9][ty][tx] = e.cf;
-  s[10][ty][tx] = e.vn;
-  s[11][ty][tx] = e.sq;
-#pragma unroll
-  for (int c = 0; c < NV; ++c) s[12 + c][ty][tx] = U[c];
-}
-__device__ __forceinline__ void get_xrec(double (*s)[CBY][CBX], int ty, int tx, DirEval& e, double U[NV]) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) e.F[c] = s[c][ty][tx];
-  e.sr = s[8][ty][tx];
-  e.cf = s[9][ty][tx];
-  e.vn = s[10][ty][tx];
-  e.sq = s[11][ty][tx];
-#pragma unroll
-  for (int c = 0; c < NV; ++c) U[c] = s[12 + c][ty][tx];
-}
 
 // Simpson flux over the edge points w0, w1, w2 (Section 2.2), LLF flux of
 // the adjacent averages (eq. 2d_llf_flux) and the sensor blend: returns
@@ -539,21 +553,31 @@ __device__ __forceinline__ double sensor_theta(double kappa, const double* a, co
   return exp(-kappa * (p1 * p2 + p3));
 }
 
-__global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __restrict__ un,
-                                               double* __restrict__ out, const double* dtp, double ca, double cb,
-                                               Counters* cn) {
-  __shared__ double s_x[XF][CBY][CBX];
+__global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __restrict__ centre,
+                                               const double* __restrict__ un, double* __restrict__ out,
+                                               const double* dtp, double ca, double cb, Counters* cn, int ntx,
+                                               int nty) {
+  // s_dfx / s_dfy: theta^s (F_simpson - F^LLF) at the x-interface left of /
+  // the y-interface below each thread's cell; they give H_L, H_R, H_D, H_U.
+  __shared__ double s_dfx[NV][CBY][CBX];
+  __shared__ double s_dfy[NV][CBY][CBX];
+  __shared__ double s_x[RF][CBY][CBX];  // exchange: primitives, records, F^LLF, Lambda
+  __shared__ double s_ts[2][CBY][CBX];  // theta^s at the two interfaces
   __shared__ double s_phi[CBY + 1][CBX + 1][4];
+  int bx, by;
+  if (!xcd_tile(ntx, nty, bx, by)) return;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * CBX + tx;
-  const int i0 = (int)blockIdx.x * (CBX - 3) - 1, j0 = (int)blockIdx.y * (CBY - 3) - 1;
+  const int i0 = bx * (CBX - 3) - 1, j0 = by * (CBY - 3) - 1;
   const int i = clamp_cell(i0 + tx, g.nx), j = clamp_cell(j0 + ty, g.ny);
   const bool output = tx >= 1 && tx < CBX - 2 && ty >= 1 && ty < CBY - 2 && i0 + tx < g.nx && j0 + ty < g.ny;
+  const int txr = tx + 1 < CBX ? tx + 1 : tx, tyu = ty + 1 < CBY ? ty + 1 : ty;
   const double dt = *dtp;
   const double lx = dt * g.rdx, ly = dt * g.rdy;
 
   // 1a: sensor primitives on [i0-2, i0+CBX+1) x [j0-2, j0+CBY+1), aliased
   //     onto the exchange buffer
   constexpr int PW = CBX + 3, PH = CBY + 3;
+  static_assert(5 * PW * PH <= RF * CBX * CBY, "primitives must fit the exchange buffer");
   double* prim = &s_x[0][0][0];
   for (int it = tid; it < PW * PH; it += CNT) {
     const int a = it % PW, b = it / PW;
@@ -584,86 +608,73 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
   }
   __syncthreads();
 
-  double A[NV], G[NV], H[4][NV], w0[NV], w1[NV], w2[NV], AN[NV], Fl[NV], dF[NV];
-  DirEval eA, eN;
-  double tsmin;
+  double A[NV], G[NV], S[NV];
   ldA(g, u.a, i, j, A);
-  // 2: x-interfaces.  The cell's own evaluation is shared with its right
-  //    neighbour; the interface at the cell's left is computed here and
-  //    shared with the left neighbour.
-  eval_dir(A, g, 0, eA);
-  put_xrec(s_x, ty, tx, eA, A);
-  __syncthreads();
-  if (tx > 0) {
-    get_xrec(s_x, ty, tx - 1, eN, AN);
-  } else {
-    ldA(g, u.a, i - 1, j, AN);
-    eval_dir(AN, g, 0, eN);
-  }
-  ldV(g, u.v, i, j, w0);
-  ldX(g, u.x, i, j, w1);
-  ldV(g, u.v, i, j + 1, w2);
-  double ts = sensor_theta(g.kappa, s_phi[ty + 1][tx], s_phi[ty + 1][tx + 1], 0);
-  tsmin = ts;
-  interface_flux(g, 0, w0, w1, w2, eN, AN, eA, A, ts, Fl, dF);
-  __syncthreads();
+  // 2: nine-point source (before the interfaces: its temporaries and theirs
+  //    are never live together)
+  cell_source(g, u, centre, i, j, S);
 #pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    s_x[c][ty][tx] = Fl[c];
-    s_x[NV + c][ty][tx] = dF[c];
-    G[c] = A[c] + lx * Fl[c];
-    H[0][c] = lx * dF[c];
-  }
-  __syncthreads();
-  {
-    const int tr = tx + 1 < CBX ? tx + 1 : tx;
+  for (int c = 0; c < NV; ++c) G[c] = A[c];
+
+  // 3: interfaces.  dir 0: the x-interface left of the cell, dir 1: the
+  //    y-interface below it.  The cell's own directional evaluation is
+  //    shared with the neighbour on the other side through LDS.
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      G[c] -= lx * s_x[c][ty][tr];
-      H[1][c] = -lx * s_x[NV + c][ty][tr];
+  for (int dir = 0; dir < 2; ++dir) {
+    double Fl[NV];
+    {
+      DirEval eA, eN;
+      double AN[NV];
+      eval_dir(A, g, dir, eA);
+      put_rec(s_x, ty, tx, eA);
+      __syncthreads();
+      const int nx_ = dir == 0 ? tx - 1 : tx, ny_ = dir == 0 ? ty : ty - 1;
+      if (dir == 0) ldA(g, u.a, i - 1, j, AN); else ldA(g, u.a, i, j - 1, AN);
+      if ((dir == 0 ? tx : ty) > 0) {
+        get_rec(s_x, ny_, nx_, eN);
+      } else {
+        eval_dir(AN, g, dir, eN);
+      }
+      double w0[NV], w1[NV], w2[NV], dF[NV];
+      ldV(g, u.v, i, j, w0);
+      if (dir == 0) {
+        ldX(g, u.x, i, j, w1);
+        ldV(g, u.v, i, j + 1, w2);
+      } else {
+        ldY(g, u.y, i, j, w1);
+        ldV(g, u.v, i + 1, j, w2);
+      }
+      const double ts = dir == 0 ? sensor_theta(g.kappa, s_phi[ty + 1][tx], s_phi[ty + 1][tx + 1], 0)
+                                 : sensor_theta(g.kappa, s_phi[ty][tx + 1], s_phi[ty + 1][tx + 1], 1);
+      interface_flux(g, dir, w0, w1, w2, eN, AN, eA, A, ts, Fl, dF);
+      s_ts[dir][ty][tx] = ts;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) (dir == 0 ? s_dfx : s_dfy)[c][ty][tx] = dF[c];
     }
-    tsmin = fmin(tsmin, sensor_theta(g.kappa, s_phi[ty + 1][tx + 1], s_phi[ty + 1][tx + 2 <= CBX ? tx + 2 : CBX], 0));
-  }
-  __syncthreads();
-  // 3: y-interfaces, the same with the neighbour below/above
-  eval_dir(A, g, 1, eA);
-  put_xrec(s_x, ty, tx, eA, A);
-  __syncthreads();
-  if (ty > 0) {
-    get_xrec(s_x, ty - 1, tx, eN, AN);
-  } else {
-    ldA(g, u.a, i, j - 1, AN);
-    eval_dir(AN, g, 1, eN);
-  }
-  ldV(g, u.v, i, j, w0);
-  ldY(g, u.y, i, j, w1);
-  ldV(g, u.v, i + 1, j, w2);
-  ts = sensor_theta(g.kappa, s_phi[ty][tx + 1], s_phi[ty + 1][tx + 1], 1);
-  tsmin = fmin(tsmin, ts);
-  interface_flux(g, 1, w0, w1, w2, eN, AN, eA, A, ts, Fl, dF);
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    s_x[c][ty][tx] = Fl[c];
-    s_x[NV + c][ty][tx] = dF[c];
-    G[c] += ly * Fl[c];
-    H[2][c] = ly * dF[c];
-  }
-  __syncthreads();
-  {
-    const int tu = ty + 1 < CBY ? ty + 1 : ty;
+    for (int c = 0; c < NV; ++c) s_x[c][ty][tx] = Fl[c];
+    __syncthreads();
+    const double lam = dir == 0 ? lx : ly;
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      G[c] -= ly * s_x[c][tu][tx];
-      H[3][c] = -ly * s_x[NV + c][tu][tx];
+    for (int c = 0; c < NV; ++c) G[c] += lam * (Fl[c] - (dir == 0 ? s_x[c][ty][txr] : s_x[c][tyu][tx]));
+    __syncthreads();
+  }
+  // H_I(c): anti-diffusive updates of the four interfaces
+  auto H = [&](int I, int c) -> double {
+    switch (I) {
+      case 0: return lx * s_dfx[c][ty][tx];
+      case 1: return -lx * s_dfx[c][ty][txr];
+      case 2: return ly * s_dfy[c][ty][tx];
+      default: return -ly * s_dfy[c][tyu][tx];
     }
-    tsmin = fmin(tsmin, sensor_theta(g.kappa, s_phi[ty + 1][tx + 1], s_phi[ty + 2 <= CBY ? ty + 2 : CBY][tx + 1], 1));
-  }
-  // 4: sources and flux-limiter steps (1)-(2)
-  double S[NV], Sl[NV], Allf[NV], Asrc[NV];
-  cell_source(g, u, i, j, A, S);
+  };
+  const double tsmin = fmin(fmin(s_ts[0][ty][tx], s_ts[0][ty][txr]), fmin(s_ts[1][ty][tx], s_ts[1][tyu][tx]));
+
+  // 4: LLF source, sensor blend of the source, flux-limiter steps (1)-(2)
+  double Sl[NV], Allf[NV], Asrc[NV];
   {
-    double P[NV], b;
+    double P[NV], AN[NV], b;
     ldA(g, u.a, i + 1, j, AN);
     b = AN[4];
     ldA(g, u.a, i - 1, j, AN);
@@ -717,7 +728,6 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
   double Lam[4];
   limiter_box(A1, H, g.gm1, er, ep, Lam, cn, output);
   // 5: unique interface coefficients and the limited update
-  __syncthreads();
 #pragma unroll
   for (int I = 0; I < 4; ++I) s_x[I][ty][tx] = Lam[I];
   __syncthreads();
@@ -733,7 +743,7 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
   double An[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c)
-    An[c] = G[c] - dt * S[c] + thL * H[0][c] + thR * H[1][c] + thD * H[2][c] + thU * H[3][c];
+    An[c] = G[c] - dt * S[c] + thL * H(0, c) + thR * H(1, c) + thD * H(2, c) + thU * H(3, c);
   if (!in_G(An, g.gm1)) count(&cn->n_not_admissible);
   const long off = (long)j * g.nx + i;
   if (ca == 0.0) {
@@ -851,11 +861,30 @@ inline int nblocks(long n) { return (int)((n + BLK - 1) / BLK); }
 }  // namespace
 
 // =================================================================== C ABI
+// Optional per-kernel timing (AF_FLAG_KERNEL_TIMING): a pair of events
+// recorded on the context's stream around each launch; pairs are folded
+// into totals when the pool is full and on af_mhd_kernel_times.
+struct KernelTimer {
+  enum { POINTS = 0, CELLS = 1, DT = 2, NKIND = 3, POOL = 1024 };
+  hipEvent_t ev[2 * POOL];
+  int kind[POOL];
+  int created = 0, used = 0;
+  double ms[NKIND] = {0.0, 0.0, 0.0};
+  long long n[NKIND] = {0, 0, 0};
+};
+
 struct af_mhd_ctx {
   Geo g;
   WS ws;
   hipStream_t stream;
   std::string err;
+  KernelTimer* timer = nullptr;
+  ~af_mhd_ctx() {
+    if (timer) {
+      for (int q = 0; q < timer->created; ++q) (void)hipEventDestroy(timer->ev[q]);
+      delete timer;
+    }
+  }
 };
 
 namespace {
@@ -870,8 +899,41 @@ bool valid_params(const af_mhd_params* p) {
   if ((p->bc_x != AF_BC_PERIODIC && p->bc_x != AF_BC_OUTFLOW) ||
       (p->bc_y != AF_BC_PERIODIC && p->bc_y != AF_BC_OUTFLOW))
     return false;
-  return p->flags == 0;
+  return (p->flags & ~(uint32_t)AF_FLAG_KERNEL_TIMING) == 0;
 }
+
+// Fold every recorded pair into the totals (synchronises on the last event).
+hipError_t timer_fold(KernelTimer* t) {
+  if (!t || t->used == 0) return hipSuccess;
+  hipError_t e = hipEventSynchronize(t->ev[2 * t->used - 1]);
+  for (int q = 0; q < t->used && e == hipSuccess; ++q) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, t->ev[2 * q], t->ev[2 * q + 1]);
+    t->ms[t->kind[q]] += ms;
+    t->n[t->kind[q]] += 1;
+  }
+  t->used = 0;
+  return e;
+}
+
+// Start event of a timed launch of the given kind (nullptr when timing is
+// off); the matching end event is returned through *end.
+hipError_t timer_begin(af_mhd_ctx* c, int kind, hipEvent_t* end) {
+  *end = nullptr;
+  KernelTimer* t = c->timer;
+  if (!t) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (t->used == KernelTimer::POOL) e = timer_fold(t);
+  const int q = t->used;
+  while (e == hipSuccess && t->created < 2 * (q + 1)) e = hipEventCreate(&t->ev[t->created++]);
+  if (e == hipSuccess) e = hipEventRecord(t->ev[2 * q], c->stream);
+  if (e != hipSuccess) return e;
+  t->kind[q] = kind;
+  t->used = q + 1;
+  *end = t->ev[2 * q + 1];
+  return hipSuccess;
+}
+hipError_t timer_end(af_mhd_ctx* c, hipEvent_t end) { return end ? hipEventRecord(end, c->stream) : hipSuccess; }
 
 void make_geo(const af_mhd_params* p, Geo& g) {
   g.nx = p->nx;
@@ -908,12 +970,21 @@ size_t layout(const Geo& g, char* base, WS* ws) {
   const size_t sizes[4] = {(size_t)g.sc, (size_t)g.sx, (size_t)g.sy, (size_t)g.sv};
   for (int k = 0; k < 2; ++k)
     for (int q = 0; q < 4; ++q) w.scratch[k][q] = take(8 * sizes[q]);
+  w.centre = take(8 * sizes[0]);
   if (ws) *ws = w;
   return off;
 }
 
+// Message of the last failed af_mhd_init on this thread (no context exists).
+thread_local std::string init_err;
+
 int fail(af_mhd_ctx* c, int code, const char* msg) {
   if (c) c->err = msg;
+  return code;
+}
+
+int init_fail(int code, const std::string& msg) {
+  init_err = msg;
   return code;
 }
 
@@ -939,10 +1010,20 @@ int run_stage(af_mhd_ctx* c, int k, const af_mhd_state* un, const af_mhd_state* 
   const CState u = cstate(uk);
   const CState n = cstate(k == 0 ? uk : un);  // not read when a_k = 0
   const MState o{out->cell, out->xface, out->yface, out->vert};
-  const dim3 pgrid((g.nxp + PB - 3) / (PB - 2), (g.nyp + PB - 3) / (PB - 2));
-  k_points<<<pgrid, dim3(PB, PB), 0, s>>>(g, u, n, o, dt_dev, A[k], B[k], c->ws.cnt);
-  const dim3 cgrid((g.nx + CBX - 4) / (CBX - 3), (g.ny + CBY - 4) / (CBY - 3));
-  k_cells<<<cgrid, dim3(CBX, CBY), 0, s>>>(g, u, n.a, o.a, dt_dev, A[k], B[k], c->ws.cnt);
+  const int ptx = (g.nxp + PB - 3) / (PB - 2), pty = (g.nyp + PB - 3) / (PB - 2);
+  hipEvent_t end;
+  hipError_t e = timer_begin(c, KernelTimer::POINTS, &end);
+  if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
+  k_points<<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(g, u, n, o, c->ws.centre, dt_dev, A[k], B[k], c->ws.cnt,
+                                                       ptx, pty);
+  e = timer_end(c, end);
+  if (e == hipSuccess) e = timer_begin(c, KernelTimer::CELLS, &end);
+  if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
+  const int ctx_ = (g.nx + CBX - 4) / (CBX - 3), cty = (g.ny + CBY - 4) / (CBY - 3);
+  k_cells<<<xcd_grid(ctx_, cty), dim3(CBX, CBY), 0, s>>>(g, u, c->ws.centre, n.a, o.a, dt_dev, A[k], B[k],
+                                                         c->ws.cnt, ctx_, cty);
+  e = timer_end(c, end);
+  if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   return check_hip(c, "stage launch");
 }
 
@@ -950,8 +1031,13 @@ int run_dt(af_mhd_ctx* c, const af_mhd_state* u, double t_rem, double* dt_dev) {
   const Geo& g = c->g;
   const long n = g.sc + g.sx + g.sy + g.sv;
   const int nb = (int)std::min<long>(RED_BLOCKS, std::max<long>(1, nblocks(n)));
+  hipEvent_t end;
+  hipError_t e = timer_begin(c, KernelTimer::DT, &end);
+  if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   k_dt_partial<<<nb, BLK, 0, c->stream>>>(g, cstate(u), c->ws.partial);
   k_dt_final<<<1, BLK, 0, c->stream>>>(c->ws.partial, nb, g.cfl, t_rem, dt_dev);
+  e = timer_end(c, end);
+  if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   return check_hip(c, "dt launch");
 }
 
@@ -968,22 +1054,33 @@ size_t af_mhd_workspace_bytes(const af_mhd_params* p) {
 
 int af_mhd_init(const af_mhd_params* p, void* workspace_dev, size_t workspace_bytes, void* hip_stream,
                 af_mhd_ctx** out) {
-  if (!out) return AF_EINVAL;
-  if (!valid_params(p)) return AF_EINVAL;
-  if (!workspace_dev || ((uintptr_t)workspace_dev & 255)) return AF_EINVAL;
+  init_err.clear();
+  if (!out) return init_fail(AF_EINVAL, "af_mhd_init: null output");
+  if (!valid_params(p)) return init_fail(AF_EINVAL, "af_mhd_init: invalid parameters");
+  if (!workspace_dev || ((uintptr_t)workspace_dev & 255))
+    return init_fail(AF_EINVAL, "af_mhd_init: workspace null or not 256-byte aligned");
   af_mhd_ctx* c = new (std::nothrow) af_mhd_ctx();
-  if (!c) return AF_EINVAL;
+  if (!c) return init_fail(AF_EINVAL, "af_mhd_init: out of host memory");
   make_geo(p, c->g);
   const size_t need = layout(c->g, nullptr, nullptr);
   if (workspace_bytes < need) {
     delete c;
-    return AF_EWORKSPACE;
+    return init_fail(AF_EWORKSPACE, "af_mhd_init: workspace too small");
   }
   layout(c->g, static_cast<char*>(workspace_dev), &c->ws);
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (p->flags & AF_FLAG_KERNEL_TIMING) {
+    c->timer = new (std::nothrow) KernelTimer();
+    if (!c->timer) {
+      delete c;
+      return init_fail(AF_EINVAL, "af_mhd_init: out of host memory");
+    }
+  }
+  (void)hipGetLastError();  // report only what this launch raises
   k_zero_counters<<<1, 64, 0, c->stream>>>(c->ws.cnt);
-  const int rc = check_hip(c, "init");
+  const int rc = check_hip(c, "af_mhd_init");
   if (rc != AF_OK) {
+    init_fail(rc, c->err);
     delete c;
     return rc;
   }
@@ -1073,8 +1170,30 @@ int af_mhd_stats(af_mhd_ctx* c, const af_mhd_state* u, af_mhd_stats_t* out) {
   return bad > 0.0 ? AF_ENOTADMISSIBLE : AF_OK;
 }
 
+int af_mhd_kernel_times(af_mhd_ctx* c, af_mhd_kernel_times_t* out, int reset) {
+  if (!c) return AF_EINVAL;
+  if (!out || !c->timer) return fail(c, AF_EINVAL, "af_mhd_kernel_times: timing not enabled or null output");
+  const hipError_t e = timer_fold(c->timer);
+  if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
+  KernelTimer* t = c->timer;
+  out->ms_points = t->ms[KernelTimer::POINTS];
+  out->ms_cells = t->ms[KernelTimer::CELLS];
+  out->ms_dt = t->ms[KernelTimer::DT];
+  out->n_points = t->n[KernelTimer::POINTS];
+  out->n_cells = t->n[KernelTimer::CELLS];
+  out->n_dt = t->n[KernelTimer::DT];
+  if (reset) {
+    for (int q = 0; q < KernelTimer::NKIND; ++q) {
+      t->ms[q] = 0.0;
+      t->n[q] = 0;
+    }
+  }
+  c->err.clear();
+  return AF_OK;
+}
+
 void af_mhd_destroy(af_mhd_ctx* c) { delete c; }
 
-const char* af_mhd_last_error(const af_mhd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* af_mhd_last_error(const af_mhd_ctx* c) { return c ? c->err.c_str() : init_err.c_str(); }
 
 }  // extern "C"

@@ -1,0 +1,105 @@
+"""Summaries of rocprofv3 CSV output (``--output-format csv``) for the
+library's kernels: per-kernel launch statistics from ``*_kernel_stats.csv``
+and, from ``*_counter_collection.csv`` files, HBM traffic per launch scaled
+against a plain copy kernel of known size.
+
+  python -m paper_2506_04857_amd.rocprof_summary kernels STATS_CSV
+  python -m paper_2506_04857_amd.rocprof_summary traffic --kernel k_cells \\
+      --fetch FETCH_CSV --write WRITE_CSV --copy-fetch CSV --copy-write CSV --copy-bytes N
+
+FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; the copy kernel reads
+and writes N bytes per dispatch, so each counter's scale factor is
+(N / 1024) / (its reading on the copy kernel).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import os
+import sys
+from collections import defaultdict
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            yield {k.strip().lower(): (v.strip() if isinstance(v, str) else v) for k, v in r.items() if k}
+
+
+def _short(name: str) -> str:
+    return name.replace("(anonymous namespace)::", "").split("(")[0].split("<")[0].strip()
+
+
+def kernel_stats(path):
+    out = []
+    for r in _rows(path):
+        out.append((_short(r["name"]), int(r["calls"]), float(r["averagens"]) / 1e3, float(r["minns"]) / 1e3,
+                    float(r["maxns"]) / 1e3, float(r["percentage"])))
+    return out
+
+
+def counter_per_dispatch(path, counter: str):
+    """{short kernel name: mean over dispatches of the counter's value}."""
+    per = defaultdict(float)
+    kern = {}
+    for r in _rows(path):
+        if r.get("counter_name") != counter:
+            continue
+        d = r["dispatch_id"]
+        per[d] += float(r["counter_value"])  # several rows per dispatch are summed
+        kern[d] = _short(r["kernel_name"])
+    agg = defaultdict(list)
+    for d, v in per.items():
+        agg[kern[d]].append(v)
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def _copy_value(table):
+    keys = [k for k in table if "copy" in k.lower()]
+    if not keys:
+        raise SystemExit("no copy kernel in the calibration counters")
+    return max(table[k] for k in keys)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("kernels")
+    a.add_argument("stats_csv")
+    b = sub.add_parser("traffic")
+    b.add_argument("--kernel", required=True)
+    for f in ("fetch", "write", "copy-fetch", "copy-write"):
+        b.add_argument("--" + f, required=True)
+    b.add_argument("--copy-bytes", type=float, required=True)
+    args = ap.parse_args(argv)
+    if args.cmd == "kernels":
+        print(f"{'kernel':<24} {'calls':>6} {'avg us':>10} {'min us':>10} {'max us':>10} {'share %':>8}")
+        for k in kernel_stats(args.stats_csv):
+            print(f"{k[0]:<24} {k[1]:>6d} {k[2]:>10.2f} {k[3]:>10.2f} {k[4]:>10.2f} {k[5]:>8.2f}")
+        return
+    fetch = counter_per_dispatch(args.fetch, "FETCH_SIZE")
+    write = counter_per_dispatch(args.write, "WRITE_SIZE")
+    cf = _copy_value(counter_per_dispatch(args.copy_fetch, "FETCH_SIZE"))
+    cw = _copy_value(counter_per_dispatch(args.copy_write, "WRITE_SIZE"))
+    sf = args.copy_bytes / 1024.0 / cf
+    sw = args.copy_bytes / 1024.0 / cw
+    kf, kw = fetch[args.kernel], write[args.kernel]
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from bench import source_hash
+    print(f"kernel: {args.kernel}")
+    print(f"fetch_kib_per_dispatch: {kf:.1f}")
+    print(f"write_kib_per_dispatch: {kw:.1f}")
+    print(f"copy_bytes: {args.copy_bytes:.0f}")
+    print(f"copy_fetch_kib: {cf:.1f}")
+    print(f"copy_write_kib: {cw:.1f}")
+    print(f"fetch_scale: {sf:.4f}")
+    print(f"write_scale: {sw:.4f}")
+    print(f"traffic_bytes_per_launch: {1024.0 * (kf * sf + kw * sw):.0f}")
+    for k in sorted(fetch):
+        if k in write:
+            print(f"# {k}: fetch {fetch[k]:.1f} KiB, write {write[k]:.1f} KiB per dispatch (unscaled)")
+    print(f"source_sha256: {source_hash()}")
+
+
+if __name__ == "__main__":
+    main()
