@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libaf_mhd.so")
+# AF_MHD_LIB selects another build of the same library (e.g. for A/B timing)
+LIB_PATH = os.environ.get("AF_MHD_LIB") or os.path.join(_PKG, "libaf_mhd.so")
 
 AF_OK, AF_EINVAL, AF_EHIP, AF_EWORKSPACE, AF_ENOTADMISSIBLE = 0, -1, -2, -3, -4
 AF_BC_PERIODIC, AF_BC_OUTFLOW = 0, 1
