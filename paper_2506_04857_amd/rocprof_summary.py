@@ -4,7 +4,7 @@ and, from ``*_counter_collection.csv`` files, HBM traffic per launch scaled
 against a plain copy kernel of known size.
 
   python -m paper_2506_04857_amd.rocprof_summary kernels STATS_CSV
-  python -m paper_2506_04857_amd.rocprof_summary traffic --kernel k_cells \\
+  python -m paper_2506_04857_amd.rocprof_summary traffic \\
       --fetch FETCH_CSV --write WRITE_CSV --copy-fetch CSV --copy-write CSV --copy-bytes N
 
 FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; the copy kernel reads
@@ -67,7 +67,6 @@ def main(argv=None):
     a = sub.add_parser("kernels")
     a.add_argument("stats_csv")
     b = sub.add_parser("traffic")
-    b.add_argument("--kernel", required=True)
     for f in ("fetch", "write", "copy-fetch", "copy-write"):
         b.add_argument("--" + f, required=True)
     b.add_argument("--copy-bytes", type=float, required=True)
@@ -83,21 +82,18 @@ def main(argv=None):
     cw = _copy_value(counter_per_dispatch(args.copy_write, "WRITE_SIZE"))
     sf = args.copy_bytes / 1024.0 / cf
     sw = args.copy_bytes / 1024.0 / cw
-    kf, kw = fetch[args.kernel], write[args.kernel]
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from bench import source_hash
-    print(f"kernel: {args.kernel}")
-    print(f"fetch_kib_per_dispatch: {kf:.1f}")
-    print(f"write_kib_per_dispatch: {kw:.1f}")
     print(f"copy_bytes: {args.copy_bytes:.0f}")
     print(f"copy_fetch_kib: {cf:.1f}")
     print(f"copy_write_kib: {cw:.1f}")
     print(f"fetch_scale: {sf:.4f}")
     print(f"write_scale: {sw:.4f}")
-    print(f"traffic_bytes_per_launch: {1024.0 * (kf * sf + kw * sw):.0f}")
     for k in sorted(fetch):
-        if k in write:
-            print(f"# {k}: fetch {fetch[k]:.1f} KiB, write {write[k]:.1f} KiB per dispatch (unscaled)")
+        if k in write and not k.startswith(("void ", "__amd")):
+            print(f"fetch_kib_per_dispatch.{k}: {fetch[k]:.1f}")
+            print(f"write_kib_per_dispatch.{k}: {write[k]:.1f}")
+            print(f"traffic_bytes_per_launch.{k}: {1024.0 * (fetch[k] * sf + write[k] * sw):.0f}")
     print(f"source_sha256: {source_hash()}")
 
 
