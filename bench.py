@@ -138,30 +138,47 @@ def main():
     cells = prob.nx * prob.ny
     stages = 3 * args.steps
 
-    # timed region: K whole steps (dt reduction + three stages), no timing events
-    ctx = af.Context(prob)
-    u = af.to_device(u0)
-    for _ in range(args.warmup):
-        ctx.af_mhd_step(u)
-    ms = timed_steps(ctx, u, args.steps, ctx.stream)
-    st = ctx.af_mhd_stats(u)
-    ctx.close()
+    def run(flags):
+        """Timed region: K whole steps (dt reduction + three stages) after W
+        warm-up steps, no timing events; then the same with per-kernel HIP
+        events on the launch stream (AF_FLAG_KERNEL_TIMING) for the kernels'
+        average launch durations.  Returns (ms, stats, final state, us)."""
+        ctx = af.Context(prob, flags=flags)
+        u = af.to_device(u0)
+        for _ in range(args.warmup):
+            ctx.af_mhd_step(u)
+        ms = timed_steps(ctx, u, args.steps, ctx.stream)
+        st = ctx.af_mhd_stats(u)
+        ctx.close()
+        tctx = af.Context(prob, flags=flags | af.AF_FLAG_KERNEL_TIMING)
+        v = af.to_device(u0)
+        for _ in range(args.warmup):
+            tctx.af_mhd_step(v)
+        tctx.af_mhd_kernel_times(reset=True)
+        timed_steps(tctx, v, args.steps, tctx.stream)
+        kt = tctx.af_mhd_kernel_times()
+        tctx.close()
+        us = {"k_cells": 1e3 * kt["ms_cells"] / max(kt["n_cells"], 1),
+              "k_points": 1e3 * kt["ms_points"] / max(kt["n_points"], 1),
+              "dt": 1e3 * kt["ms_dt"] / max(kt["n_dt"], 1)}
+        return ms, st, af.to_host(u), us
+
+    ms, st, u64, us = run(0)
     t_stage = ms * 1e-3 / stages
     value = cells / t_stage
 
-    # second pass with per-kernel HIP events on the launch stream: the
-    # dominant kernel's average launch duration for the roofline
-    tctx = af.Context(prob, flags=af.AF_FLAG_KERNEL_TIMING)
-    u = af.to_device(u0)
-    for _ in range(args.warmup):
-        tctx.af_mhd_step(u)
-    tctx.af_mhd_kernel_times(reset=True)
-    timed_steps(tctx, u, args.steps, tctx.stream)
-    kt = tctx.af_mhd_kernel_times()
-    tctx.close()
-    us = {"k_cells": 1e3 * kt["ms_cells"] / max(kt["n_cells"], 1),
-          "k_points": 1e3 * kt["ms_points"] / max(kt["n_points"], 1),
-          "dt": 1e3 * kt["ms_dt"] / max(kt["n_dt"], 1)}
+    # FP32-bulk stage on the same workload, and its difference from the
+    # FP64 run after the same number of steps (L1 of rho and p, relative)
+    ms32, st32, u32, us32 = run(af.AF_FLAG_FP32_BULK)
+    value32 = cells / (ms32 * 1e-3 / stages)
+
+    def pressure(A):
+        return (prob.gamma - 1) * (A[7] - 0.5 * (A[1] ** 2 + A[2] ** 2 + A[3] ** 2) / A[0]
+                                   - 0.5 * (A[4] ** 2 + A[5] ** 2 + A[6] ** 2))
+
+    l1_rho = float(abs(u32[0][0] - u64[0][0]).mean() / abs(u64[0][0]).mean())
+    p64, p32 = pressure(u64[0]), pressure(u32[0])
+    l1_p = float(abs(p32 - p64).mean() / abs(p64).mean())
     # the dominant kernel: the larger of the two stage kernels
     dom = "k_points" if us["k_points"] >= us["k_cells"] else "k_cells"
     algo = (BYTES_PER_CELL_POINTS if dom == "k_points" else BYTES_PER_CELL_CELLS) * cells
@@ -190,6 +207,11 @@ def main():
         "kernels_us": us,
         "stage_hbm_gbs": BYTES_PER_CELL_STAGE * cells / t_stage / 1e9,
         "admissible": bool(st["admissible"]),
+        "fp32_bulk": {"value": value32, "unit": UNIT, "speedup_vs_fp64": value32 / value,
+                      "ms_per_step": ms32 / args.steps, "kernels_us": us32,
+                      "admissible": bool(st32["admissible"]),
+                      "l1_rel_vs_fp64": {"rho": l1_rho, "p": l1_p},
+                      "compared_after_steps": args.warmup + args.steps},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, u0)

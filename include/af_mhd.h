@@ -61,8 +61,17 @@ typedef struct {
   double cfl;               /* dt = cfl / max over all DoFs of (rho_1/dx + rho_2/dy), in (0,1] */
   double kappa;             /* shock-sensor strength (Section 3.4), >= 0; 0 disables the sensor */
   int32_t bc_x, bc_y;       /* AF_BC_PERIODIC or AF_BC_OUTFLOW per direction */
-  uint32_t flags;           /* 0 or AF_FLAG_KERNEL_TIMING; other bits are rejected */
+  uint32_t flags;           /* AF_FLAG_* bits below; other bits are rejected */
 } af_mhd_params;
+
+/* FP32-bulk stage: fluxes, wave speeds, the flux-vector-splitting and LLF
+ * sums, the shock sensor and the source sums in FP32; storage, pressure
+ * recovery (the rho E - |m|^2/2 - rho |B|^2/2 cancellation), the centre
+ * value, every stage accumulation U + dt RHS, every positivity-limiter
+ * decision and the limiter's root solves stay FP64.  Results then differ
+ * from the FP64 stage at the FP32 rounding level (about 1e-7 relative per
+ * stage); the limiters still guarantee rho, p >= the paper's bounds. */
+#define AF_FLAG_FP32_BULK 1u
 
 /* Record HIP events on the context's stream around every kernel launch so
  * that af_mhd_kernel_times can report per-kernel device time.  Costs one

@@ -51,6 +51,7 @@ class af_mhd_stats_t(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+AF_FLAG_FP32_BULK = 1
 AF_FLAG_KERNEL_TIMING = 4
 
 

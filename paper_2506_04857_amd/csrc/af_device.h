@@ -94,89 +94,125 @@ __device__ __forceinline__ bool p_at_least(const double U[NV], double eps, doubl
   return gm1 * rho_p(U) >= U[0] * eps;
 }
 
+// ------------------------------------------------------ compute precision
+// The bulk arithmetic (fluxes, wave speeds, FVS and LLF sums, the shock
+// sensor, the source sums) runs in R: double for the FP64 stage, float for
+// the FP32-bulk stage.  Storage, pressure recovery, the centre value, every
+// stage accumulation U + dt RHS and every limiter decision stay FP64.
+template <class R> struct IsF32 { static constexpr bool value = false; };
+template <> struct IsF32<float> { static constexpr bool value = true; };
+
+template <class R> __device__ __forceinline__ R rcp_r(R x) { return R(1) / x; }
+template <> __device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <class R> __device__ __forceinline__ R sqrt_r(R x) { return sqrt(x); }
+template <> __device__ __forceinline__ float sqrt_r<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <class R> __device__ __forceinline__ R exp_r(R x) { return exp(x); }
+template <> __device__ __forceinline__ float exp_r<float>(float x) { return __expf(x); }
+
 // What the directional stencils need from one state: the flux in the
 // direction, its spectral radius |v_n| + c_f, c_f, v_n and sqrt(rho).
-struct DirEval {
-  double F[NV];
-  double sr, cf, vn, sq;
+template <class R>
+struct DirEvalT {
+  R F[NV];
+  R sr, cf, vn, sq;
 };
+using DirEval = DirEvalT<double>;
+
+// Velocity, |B|^2 and pressure of a state.  FP64 as written; for the
+// FP32-bulk stage the cancellation-prone part rho p/(gamma-1) = rho E -
+// |m|^2/2 - rho |B|^2/2 is formed in FP64 and only the final scaling by
+// 1/rho is FP32.
+template <class R>
+__device__ __forceinline__ void prim_r(const double U[NV], double gm1, R& ri, R& v1, R& v2, R& v3, R& b2, R& p) {
+  if constexpr (IsF32<R>::value) {
+    const double b2d = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+    const double rp = U[0] * (U[7] - 0.5 * b2d) - 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]);
+    ri = rcp_r((float)U[0]);
+    v1 = (float)U[1] * ri;
+    v2 = (float)U[2] * ri;
+    v3 = (float)U[3] * ri;
+    b2 = (float)b2d;
+    p = (float)(gm1 * rp) * ri;
+  } else {
+    ri = 1.0 / U[0];
+    v1 = U[1] * ri;
+    v2 = U[2] * ri;
+    v3 = U[3] * ri;
+    b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+    p = gm1 * (U[7] - 0.5 * (U[1] * v1 + U[2] * v2 + U[3] * v3) - 0.5 * b2);
+  }
+}
 
 // Flux F_n = v_n U + p_t (e_{m_n} + v_n e_E) - B_n (0, B, v, v.B): the
 // physical flux of Section 1 regrouped (transport, total pressure, tension).
-__device__ __forceinline__ void eval_dir(const double U[NV], const Geo& g, int dir, DirEval& e) {
-  const double ri = 1.0 / U[0];
-  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
-  const double B1 = U[4], B2 = U[5], B3 = U[6];
-  const double b2 = B1 * B1 + B2 * B2 + B3 * B3;
-  const double p = g.gm1 * (U[7] - 0.5 * (U[1] * v1 + U[2] * v2 + U[3] * v3) - 0.5 * b2);
-  const double pt = p + 0.5 * b2;
-  const double vB = v1 * B1 + v2 * B2 + v3 * B3;
-  const double vn = dir ? v2 : v1;
-  const double Bn = dir ? B2 : B1;
-  e.F[0] = U[0] * vn;
-  e.F[1] = vn * U[1] - Bn * B1 + (dir ? 0.0 : pt);
-  e.F[2] = vn * U[2] - Bn * B2 + (dir ? pt : 0.0);
-  e.F[3] = vn * U[3] - Bn * B3;
-  e.F[4] = dir ? (vn * B1 - Bn * v1) : 0.0;
-  e.F[5] = dir ? 0.0 : (vn * B2 - Bn * v2);
-  e.F[6] = vn * B3 - Bn * v3;
-  e.F[7] = (U[7] + pt) * vn - Bn * vB;
+template <class R>
+__device__ __forceinline__ void flux_from(const double U[NV], int dir, R v1, R v2, R v3, R pt, R F[NV]) {
+  const R B1 = (R)U[4], B2 = (R)U[5], B3 = (R)U[6];
+  const R vB = v1 * B1 + v2 * B2 + v3 * B3;
+  const R vn = dir ? v2 : v1;
+  const R Bn = dir ? B2 : B1;
+  F[0] = (R)U[0] * vn;
+  F[1] = vn * (R)U[1] - Bn * B1 + (dir ? R(0) : pt);
+  F[2] = vn * (R)U[2] - Bn * B2 + (dir ? pt : R(0));
+  F[3] = vn * (R)U[3] - Bn * B3;
+  F[4] = dir ? (vn * B1 - Bn * v1) : R(0);
+  F[5] = dir ? R(0) : (vn * B2 - Bn * v2);
+  F[6] = vn * B3 - Bn * v3;
+  F[7] = ((R)U[7] + pt) * vn - Bn * vB;
+}
+
+template <class R>
+__device__ __forceinline__ void eval_dir(const double U[NV], const Geo& g, int dir, DirEvalT<R>& e) {
+  R ri, v1, v2, v3, b2, p;
+  prim_r<R>(U, g.gm1, ri, v1, v2, v3, b2, p);
+  const R pt = p + R(0.5) * b2;
+  flux_from<R>(U, dir, v1, v2, v3, pt, e.F);
+  const R vn = dir ? v2 : v1;
+  const R Bn = dir ? (R)U[5] : (R)U[4];
   // fast magnetosonic speed, eq. (cf)
-  const double c2 = g.gamma * p * ri;
-  const double s = c2 + b2 * ri;
-  double disc = s * s - 4.0 * c2 * Bn * Bn * ri;
-  disc = disc > 0.0 ? disc : 0.0;
-  e.cf = sqrt(0.5 * (s + sqrt(disc)));
+  const R c2 = (R)g.gamma * p * ri;
+  const R s = c2 + b2 * ri;
+  R disc = s * s - R(4) * c2 * Bn * Bn * ri;
+  disc = disc > R(0) ? disc : R(0);
+  e.cf = sqrt_r(R(0.5) * (s + sqrt_r(disc)));
   e.vn = vn;
   e.sr = fabs(vn) + e.cf;
-  e.sq = sqrt(U[0]);
+  e.sq = sqrt_r((R)U[0]);
 }
 
 // Flux only (central differences and Simpson fluxes need no wave speed).
-__device__ __forceinline__ void flux_dir(const double U[NV], double gm1, int dir, double F[NV]) {
-  const double ri = 1.0 / U[0];
-  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
-  const double B1 = U[4], B2 = U[5], B3 = U[6];
-  const double b2 = B1 * B1 + B2 * B2 + B3 * B3;
-  const double p = gm1 * (U[7] - 0.5 * (U[1] * v1 + U[2] * v2 + U[3] * v3) - 0.5 * b2);
-  const double pt = p + 0.5 * b2;
-  const double vB = v1 * B1 + v2 * B2 + v3 * B3;
-  const double vn = dir ? v2 : v1;
-  const double Bn = dir ? B2 : B1;
-  F[0] = U[0] * vn;
-  F[1] = vn * U[1] - Bn * B1 + (dir ? 0.0 : pt);
-  F[2] = vn * U[2] - Bn * B2 + (dir ? pt : 0.0);
-  F[3] = vn * U[3] - Bn * B3;
-  F[4] = dir ? (vn * B1 - Bn * v1) : 0.0;
-  F[5] = dir ? 0.0 : (vn * B2 - Bn * v2);
-  F[6] = vn * B3 - Bn * v3;
-  F[7] = (U[7] + pt) * vn - Bn * vB;
+template <class R>
+__device__ __forceinline__ void flux_dir(const double U[NV], double gm1, int dir, R F[NV]) {
+  R ri, v1, v2, v3, b2, p;
+  prim_r<R>(U, gm1, ri, v1, v2, v3, b2, p);
+  flux_from<R>(U, dir, v1, v2, v3, p + R(0.5) * b2, F);
 }
 
 // Godunov-Powell vector Psi = (0, B, v, v.B), eq. (gp_src).
-__device__ __forceinline__ void psi(const double U[NV], double P[NV]) {
-  const double ri = 1.0 / U[0];
-  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
-  P[0] = 0.0;
-  P[1] = U[4];
-  P[2] = U[5];
-  P[3] = U[6];
+template <class R>
+__device__ __forceinline__ void psi(const double U[NV], R P[NV]) {
+  const R ri = rcp_r((R)U[0]);
+  const R v1 = (R)U[1] * ri, v2 = (R)U[2] * ri, v3 = (R)U[3] * ri;
+  P[0] = R(0);
+  P[1] = (R)U[4];
+  P[2] = (R)U[5];
+  P[3] = (R)U[6];
   P[4] = v1;
   P[5] = v2;
   P[6] = v3;
-  P[7] = v1 * U[4] + v2 * U[5] + v3 * U[6];
+  P[7] = v1 * (R)U[4] + v2 * (R)U[5] + v3 * (R)U[6];
 }
 
 // LLF viscosity of the Lemma, taken with equality: max of the two spectral
 // radii and of alpha_*(U,Ut), alpha_*(Ut,U); the latter two share all terms
 // but |v_n|, so their maximum uses max(|v_a|, |v_b|, |Roe-type average|).
-__device__ __forceinline__ double alpha_llf(const DirEval& a, const DirEval& b, const double Ua[NV],
-                                            const double Ub[NV]) {
-  const double inv = 1.0 / (a.sq + b.sq);
-  const double roe = fabs(a.sq * a.vn + b.sq * b.vn) * inv;
-  const double d1 = Ua[4] - Ub[4], d2 = Ua[5] - Ub[5], d3 = Ua[6] - Ub[6];
-  const double jump = sqrt(d1 * d1 + d2 * d2 + d3 * d3) * inv;
-  const double al = (fmax(fmax(fabs(a.vn), fabs(b.vn)), roe) + fmax(a.cf, b.cf)) + jump;
+template <class R, class S>
+__device__ __forceinline__ R alpha_llf(const DirEvalT<R>& a, const DirEvalT<R>& b, const S Ua[NV], const S Ub[NV]) {
+  const R inv = rcp_r(a.sq + b.sq);
+  const R roe = fabs(a.sq * a.vn + b.sq * b.vn) * inv;
+  const R d1 = (R)(Ua[4] - Ub[4]), d2 = (R)(Ua[5] - Ub[5]), d3 = (R)(Ua[6] - Ub[6]);
+  const R jump = sqrt_r(d1 * d1 + d2 * d2 + d3 * d3) * inv;
+  const R al = (fmax(fmax(fabs(a.vn), fabs(b.vn)), roe) + fmax(a.cf, b.cf)) + jump;
   return fmax(al, fmax(a.sr, b.sr));
 }
 

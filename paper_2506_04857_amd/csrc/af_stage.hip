@@ -81,8 +81,8 @@ __device__ double sensor_pressure(const double U[NV], double gamma) {
 constexpr int PB = 16, PNT = PB * PB;
 constexpr int RF = 12;  // record: F[8], sr, cf, vn, sq
 
-template <int W, int H>
-__device__ __forceinline__ void put_rec(double (*s)[H][W], int ty, int tx, const DirEval& e) {
+template <int W, int H, class R>
+__device__ __forceinline__ void put_rec(R (*s)[H][W], int ty, int tx, const DirEvalT<R>& e) {
 #pragma unroll
   for (int c = 0; c < NV; ++c) s[c][ty][tx] = e.F[c];
   s[8][ty][tx] = e.sr;
@@ -90,8 +90,8 @@ __device__ __forceinline__ void put_rec(double (*s)[H][W], int ty, int tx, const
   s[10][ty][tx] = e.vn;
   s[11][ty][tx] = e.sq;
 }
-template <int W, int H>
-__device__ __forceinline__ void get_rec(double (*s)[H][W], int ty, int tx, DirEval& e) {
+template <int W, int H, class R>
+__device__ __forceinline__ void get_rec(R (*s)[H][W], int ty, int tx, DirEvalT<R>& e) {
 #pragma unroll
   for (int c = 0; c < NV; ++c) e.F[c] = s[c][ty][tx];
   e.sr = s[8][ty][tx];
@@ -100,7 +100,8 @@ __device__ __forceinline__ void get_rec(double (*s)[H][W], int ty, int tx, DirEv
   e.sq = s[11][ty][tx];
 }
 
-__device__ __forceinline__ void put_rec(double (*s)[PB][PB], int base, int ty, int tx, const DirEval& e) {
+template <class R>
+__device__ __forceinline__ void put_rec(R (*s)[PB][PB], int base, int ty, int tx, const DirEvalT<R>& e) {
 #pragma unroll
   for (int c = 0; c < NV; ++c) s[base + c][ty][tx] = e.F[c];
   s[base + 8][ty][tx] = e.sr;
@@ -108,7 +109,8 @@ __device__ __forceinline__ void put_rec(double (*s)[PB][PB], int base, int ty, i
   s[base + 10][ty][tx] = e.vn;
   s[base + 11][ty][tx] = e.sq;
 }
-__device__ __forceinline__ void get_rec(double (*s)[PB][PB], int base, int ty, int tx, DirEval& e) {
+template <class R>
+__device__ __forceinline__ void get_rec(R (*s)[PB][PB], int base, int ty, int tx, DirEvalT<R>& e) {
 #pragma unroll
   for (int c = 0; c < NV; ++c) e.F[c] = s[base + c][ty][tx];
   e.sr = s[base + 8][ty][tx];
@@ -120,59 +122,65 @@ __device__ __forceinline__ void get_rec(double (*s)[PB][PB], int base, int ty, i
 // Incremental FVS along a line (own point e0/U0 at offset 0).  Outer
 // neighbours (offsets -h, +h) are also the LLF neighbours; inner ones
 // (-h/2, +h/2) enter the FVS sums only.  R = (SF + alpha SW)/(2h).
+template <class R>
 struct LineAcc {
-  double SF[NV], SW[NV], G[NV];
-  double alpha, dB, jl;
+  R SF[NV], SW[NV], G[NV];
+  R alpha, dB, jl;
 };
 
-__device__ __forceinline__ void line_begin(LineAcc& L, const DirEval& e0, const double U0[NV]) {
+template <class R>
+__device__ __forceinline__ void line_begin(LineAcc<R>& L, const DirEvalT<R>& e0, const R U0[NV]) {
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
-    L.SF[c] = 0.0;
-    L.SW[c] = 6.0 * U0[c];
-    L.G[c] = 0.0;
+    L.SF[c] = R(0);
+    L.SW[c] = R(6) * U0[c];
+    L.G[c] = R(0);
   }
   L.alpha = e0.sr;
-  L.dB = 0.0;
-  L.jl = 0.0;
+  L.dB = R(0);
+  L.jl = R(0);
 }
 
 // side = -1 for the neighbour at -h (left/below), +1 at +h.
-__device__ __forceinline__ void line_outer(LineAcc& L, int bn, int side, const DirEval& e, const double U[NV],
-                                           const DirEval& e0, const double U0[NV]) {
+template <class R>
+__device__ __forceinline__ void line_outer(LineAcc<R>& L, int bn, int side, const DirEvalT<R>& e, const R U[NV],
+                                           const DirEvalT<R>& e0, const R U0[NV]) {
   L.alpha = fmax(L.alpha, e.sr);
-  const double al = side < 0 ? alpha_llf(e, e0, U, U0) : alpha_llf(e0, e, U0, U);
+  const R al = side < 0 ? alpha_llf(e, e0, U, U0) : alpha_llf(e0, e, U0, U);
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
     L.SF[c] -= side * e.F[c];
     L.SW[c] += U[c];
     // F^LLF(U0, U) for side +1, -F^LLF(U, U0) for side -1
-    L.G[c] += side < 0 ? -0.5 * (e.F[c] + e0.F[c] - al * (U0[c] - U[c]))
-                       : 0.5 * (e0.F[c] + e.F[c] - al * (U[c] - U0[c]));
+    L.G[c] += side < 0 ? R(-0.5) * (e.F[c] + e0.F[c] - al * (U0[c] - U[c]))
+                       : R(0.5) * (e0.F[c] + e.F[c] - al * (U[c] - U0[c]));
   }
   L.dB -= side * U[bn];
   L.jl += side * U[bn];
 }
 
-__device__ __forceinline__ void line_inner(LineAcc& L, int bn, int side, const DirEval& e, const double U[NV]) {
+template <class R>
+__device__ __forceinline__ void line_inner(LineAcc<R>& L, int bn, int side, const DirEvalT<R>& e, const R U[NV]) {
   L.alpha = fmax(L.alpha, e.sr);
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
-    L.SF[c] += side * 4.0 * e.F[c];
-    L.SW[c] -= 4.0 * U[c];
+    L.SF[c] += side * R(4) * e.F[c];
+    L.SW[c] -= R(4) * U[c];
   }
-  L.dB += side * 4.0 * U[bn];
+  L.dB += side * R(4) * U[bn];
 }
 
 // Point accumulators: high-order RHS h = -R_x - R_y with the div part, and
 // the LLF update l = -dt/dx G_x - dt/dy G_y with its div part.
+template <class R>
 struct PointAcc {
-  double h[NV], l[NV];
-  double divh, divl;
+  R h[NV], l[NV];
+  R divh, divl;
 };
 
-__device__ __forceinline__ void acc_fvs(PointAcc& P, const LineAcc& L, double rh, double lam) {
-  const double s = 0.5 * rh;
+template <class R>
+__device__ __forceinline__ void acc_fvs(PointAcc<R>& P, const LineAcc<R>& L, R rh, R lam) {
+  const R s = R(0.5) * rh;
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
     P.h[c] -= (L.SF[c] + L.alpha * L.SW[c]) * s;
@@ -184,37 +192,50 @@ __device__ __forceinline__ void acc_fvs(PointAcc& P, const LineAcc& L, double rh
 
 // Central direction across a face point: neighbours dn/up at -h/2, +h/2;
 // they are also its LLF neighbours.
-__device__ __forceinline__ void acc_central(PointAcc& P, int bn, double rh, double lam, const DirEval& ed,
-                                            const double dn[NV], const DirEval& e0, const double U0[NV],
-                                            const DirEval& eu, const double up[NV]) {
-  const double ad = alpha_llf(ed, e0, dn, U0), au = alpha_llf(e0, eu, U0, up);
+template <class R>
+__device__ __forceinline__ void acc_central(PointAcc<R>& P, int bn, R rh, R lam, const DirEvalT<R>& ed,
+                                            const R dn[NV], const DirEvalT<R>& e0, const R U0[NV],
+                                            const DirEvalT<R>& eu, const R up[NV]) {
+  const R ad = alpha_llf(ed, e0, dn, U0), au = alpha_llf(e0, eu, U0, up);
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
     P.h[c] -= (eu.F[c] - ed.F[c]) * rh;
-    const double G = 0.5 * (e0.F[c] + eu.F[c] - au * (up[c] - U0[c])) - 0.5 * (ed.F[c] + e0.F[c] - ad * (U0[c] - dn[c]));
+    const R G = R(0.5) * (e0.F[c] + eu.F[c] - au * (up[c] - U0[c])) - R(0.5) * (ed.F[c] + e0.F[c] - ad * (U0[c] - dn[c]));
     P.l[c] -= lam * G;
   }
   P.divh += (up[bn] - dn[bn]) * rh;
-  P.divl += 0.5 * rh * (up[bn] - dn[bn]);
+  P.divl += R(0.5) * rh * (up[bn] - dn[bn]);
 }
 
-__device__ __forceinline__ void acc_zero(PointAcc& P) {
+template <class R>
+__device__ __forceinline__ void acc_zero(PointAcc<R>& P) {
 #pragma unroll
-  for (int c = 0; c < NV; ++c) P.h[c] = P.l[c] = 0.0;
-  P.divh = P.divl = 0.0;
+  for (int c = 0; c < NV; ++c) P.h[c] = P.l[c] = R(0);
+  P.divh = P.divl = R(0);
 }
 
-// High-order and LLF states from the accumulators, scaling limiter, SSP
-// combination, store.
-__device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[NV], const PointAcc& P, double ca,
-                                      double cb, const double* __restrict__ un, double* __restrict__ out, long plane,
-                                      long off, Counters* cn) {
-  double Ps[NV], UH[NV], UL[NV], W[NV];
+// High-order and LLF states from the accumulators (the right-hand sides in
+// the compute type, the states in FP64), scaling limiter, SSP combination,
+// store.
+template <class R>
+__device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[NV], const PointAcc<R>& P,
+                                      double ca, double cb, const double* __restrict__ un, double* __restrict__ out,
+                                      long plane, long off, Counters* cn) {
+  double UH[NV], UL[NV], W[NV];
+  R Ps[NV];
   psi(U0, Ps);
+  if constexpr (IsF32<R>::value) {
 #pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    UH[c] = U0[c] + dt * (P.h[c] - P.divh * Ps[c]);
-    UL[c] = U0[c] + P.l[c] - dt * P.divl * Ps[c];
+    for (int c = 0; c < NV; ++c) {
+      UH[c] = U0[c] + dt * (double)(P.h[c] - P.divh * Ps[c]);
+      UL[c] = U0[c] + (double)(P.l[c] - (float)dt * P.divl * Ps[c]);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      UH[c] = U0[c] + dt * (P.h[c] - P.divh * Ps[c]);
+      UL[c] = U0[c] + P.l[c] - dt * P.divl * Ps[c];
+    }
   }
   if (!in_G(UL, g.gm1)) count(&cn->n_llf_not_admissible);
   limit_point(UH, UL, g.gm1, W, cn, true);
@@ -230,19 +251,31 @@ __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[
 
 __device__ __forceinline__ int clamp_pt(int i, int np) { return i < -1 ? -1 : (i > np ? np : i); }
 
-// LDS layout of k_points (fields of PB x PB doubles): raw states of the
-// tile's V, X, Y and centre values, then two directional records.
+// LDS layout of k_points (fields of PB x PB values of the compute type):
+// states of the tile's V, X, Y and centre values, then two directional
+// records.
 constexpr int SV_ = 0, SX_ = 8, SY_ = 16, SC_ = 24, SR0 = 32, SR1 = 32 + RF, SFIELDS = 32 + 2 * RF;
 
-__device__ __forceinline__ void lds8(double (*s)[PB][PB], int base, int ty, int tx, double U[NV]) {
+template <class R>
+__device__ __forceinline__ void lds8(R (*s)[PB][PB], int base, int ty, int tx, R U[NV]) {
 #pragma unroll
   for (int c = 0; c < NV; ++c) U[c] = s[base + c][ty][tx];
 }
+template <class R>
+__device__ __forceinline__ void sts8(R (*s)[PB][PB], int base, int ty, int tx, const double U[NV]) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) s[base + c][ty][tx] = (R)U[c];
+}
 
-__global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MState out, double* __restrict__ centre,
+// R = double: the FP64 stage; R = float: the FP32-bulk stage (LDS holds the
+// compute type; a thread's own states are re-read in FP64 from memory for
+// the evaluations and the FP64 accumulation).
+template <class R>
+__global__ __launch_bounds__(PNT, IsF32<R>::value ? 2 : 1) void k_points(Geo g, CState u, CState un, MState out, double* __restrict__ centre,
                                                 const double* dtp, double ca, double cb, Counters* cn, int ntx,
                                                 int nty) {
-  __shared__ double s[SFIELDS][PB][PB];
+  constexpr bool F32 = IsF32<R>::value;
+  __shared__ R s[SFIELDS][PB][PB];
   int bx, by;
   if (!xcd_tile(ntx, nty, bx, by)) return;
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -254,6 +287,7 @@ __global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MSta
   const bool outY = inner && i0 + tx < g.nx && j0 + ty < g.nyp;
   const double dt = *dtp;
   const double lx = dt * g.rdx, ly = dt * g.rdy;
+  const R rdx = (R)g.rdx, rdy = (R)g.rdy, lxr = (R)lx, lyr = (R)ly;
   const int txl = tx > 0 ? tx - 1 : tx, txr = tx < PB - 1 ? tx + 1 : tx;
   const int tyd = ty > 0 ? ty - 1 : ty, tyu = ty < PB - 1 ? ty + 1 : ty;
 
@@ -261,54 +295,88 @@ __global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MSta
   {
     double w[NV];
     ldV(g, u.v, i, j, w);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) s[SV_ + c][ty][tx] = w[c];
+    sts8(s, SV_, ty, tx, w);
     ldX(g, u.x, i, j, w);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) s[SX_ + c][ty][tx] = w[c];
+    sts8(s, SX_, ty, tx, w);
     ldY(g, u.y, i, j, w);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) s[SY_ + c][ty][tx] = w[c];
+    sts8(s, SY_, ty, tx, w);
   }
   __syncthreads();
-  // 1: centre values (the last column/row's are never used)
+  // a thread's own FP64 states (V, X, Y; the centre is kept in C64)
+  double C64[NV];
+  auto own = [&](int which, double U[NV]) {
+    if constexpr (F32) {
+      if (which == 0) ldV(g, u.v, i, j, U);
+      else if (which == 1) ldX(g, u.x, i, j, U);
+      else if (which == 2) ldY(g, u.y, i, j, U);
+      else {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) U[c] = C64[c];
+      }
+    } else {
+      lds8(s, which == 0 ? SV_ : which == 1 ? SX_ : which == 2 ? SY_ : SC_, ty, tx, U);
+    }
+  };
+  // 1: centre values in FP64 (the last column/row's are never used); the
+  //    owner also stores its value for the cell kernel's source term
   {
-    double A[NV], Uc[NV], f[NV], w[NV], q[NV], C[NV];
+    double A[NV], Uc[NV], f[NV], w[NV], q[NV];
     ldA(g, u.a, i, j, A);
-    lds8(s, SX_, ty, tx, f);
-    lds8(s, SX_, ty, txr, w);
-    lds8(s, SY_, ty, tx, Uc);
-    lds8(s, SY_, tyu, tx, q);
+    if constexpr (F32) {
+      ldX(g, u.x, i, j, f);
+      ldX(g, u.x, i + 1, j, w);
+      ldY(g, u.y, i, j, Uc);
+      ldY(g, u.y, i, j + 1, q);
+    } else {
+      lds8(s, SX_, ty, tx, f);
+      lds8(s, SX_, ty, txr, w);
+      lds8(s, SY_, ty, tx, Uc);
+      lds8(s, SY_, tyu, tx, q);
+    }
 #pragma unroll
     for (int c = 0; c < NV; ++c) f[c] = -4.0 * ((f[c] + w[c]) + (Uc[c] + q[c]));
-    lds8(s, SV_, ty, tx, Uc);
-    lds8(s, SV_, ty, txr, w);
+    if constexpr (F32) {
+      ldV(g, u.v, i, j, Uc);
+      ldV(g, u.v, i + 1, j, w);
+    } else {
+      lds8(s, SV_, ty, tx, Uc);
+      lds8(s, SV_, ty, txr, w);
+    }
 #pragma unroll
     for (int c = 0; c < NV; ++c) Uc[c] += w[c];
-    lds8(s, SV_, tyu, tx, q);
-    lds8(s, SV_, tyu, txr, w);
+    if constexpr (F32) {
+      ldV(g, u.v, i, j + 1, q);
+      ldV(g, u.v, i + 1, j + 1, w);
+    } else {
+      lds8(s, SV_, tyu, tx, q);
+      lds8(s, SV_, tyu, txr, w);
+    }
 #pragma unroll
     for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
     const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
-    limit_centre(Uc, A, g.gm1, C, cn, owner);
+    limit_centre(Uc, A, g.gm1, C64, cn, owner);
+    sts8(s, SC_, ty, tx, C64);
+    if (owner) {
 #pragma unroll
-    for (int c = 0; c < NV; ++c) s[SC_ + c][ty][tx] = C[c];
-    if (owner) {  // for the cell kernel's source term
-#pragma unroll
-      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C[c];
+      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C64[c];
     }
   }
-  PointAcc PA, PB_;
-  DirEval e0, e1, en;
-  double U0[NV], U1[NV], Un[NV];
-  LineAcc L;
+  PointAcc<R> PA, PB_;
+  DirEvalT<R> e0, e1, en;
+  R U0[NV], U1[NV], Un[NV];
+  LineAcc<R> L;
 
   // b: vertical lines through V and X.  V: FVS in y over V(l-1), X(l-1), V,
   // X(l), V(l+1).  X: central in y between V(k,j) and V(k,j+1).
+  {
+    double w[NV];
+    own(0, w);
+    eval_dir(w, g, 1, e0);
+    own(1, w);
+    eval_dir(w, g, 1, e1);
+  }
   lds8(s, SV_, ty, tx, U0);
   lds8(s, SX_, ty, tx, U1);
-  eval_dir(U0, g, 1, e0);
-  eval_dir(U1, g, 1, e1);
   put_rec(s, SR0, ty, tx, e0);
   put_rec(s, SR1, ty, tx, e1);
   __syncthreads();
@@ -325,15 +393,20 @@ __global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MSta
   get_rec(s, SR0, tyu, tx, en);
   lds8(s, SV_, tyu, tx, Un);
   line_outer(L, 5, +1, en, Un, e0, U0);
-  acc_fvs(PA, L, g.rdy, ly);
-  acc_central(PB_, 5, g.rdy, ly, e0, U0, e1, U1, en, Un);
+  acc_fvs(PA, L, rdy, lyr);
+  acc_central(PB_, 5, rdy, lyr, e0, U0, e1, U1, en, Un);
   __syncthreads();
 
   // a: horizontal lines through V and Y.  V: FVS in x over V(k-1), Y(k-1),
   // V, Y(k), V(k+1) -> V complete.  Y: central in x between V(i,l), V(i+1,l).
+  {
+    double w[NV];
+    own(0, w);
+    eval_dir(w, g, 0, e0);
+    own(2, w);
+    eval_dir(w, g, 0, e1);
+  }
   lds8(s, SY_, ty, tx, U1);
-  eval_dir(U0, g, 0, e0);
-  eval_dir(U1, g, 0, e1);
   put_rec(s, SR0, ty, tx, e0);
   put_rec(s, SR1, ty, tx, e1);
   __syncthreads();
@@ -348,18 +421,27 @@ __global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MSta
   get_rec(s, SR0, ty, txr, en);
   lds8(s, SV_, ty, txr, Un);
   line_outer(L, 4, +1, en, Un, e0, U0);
-  acc_fvs(PA, L, g.rdx, lx);
-  if (outV) finish(g, dt, U0, PA, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
+  acc_fvs(PA, L, rdx, lxr);
+  if (outV) {
+    double w[NV];
+    own(0, w);
+    finish(g, dt, w, PA, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
+  }
   acc_zero(PA);  // now Y
-  acc_central(PA, 4, g.rdx, lx, e0, U0, e1, U1, en, Un);
+  acc_central(PA, 4, rdx, lxr, e0, U0, e1, U1, en, Un);
   __syncthreads();
 
   // c: horizontal lines through X and C.  X: FVS in x over X(k-1), C(k-1),
   // X, C(k), X(k+1) -> X complete.
+  {
+    double w[NV];
+    own(1, w);
+    eval_dir(w, g, 0, e0);
+    own(3, w);
+    eval_dir(w, g, 0, e1);
+  }
   lds8(s, SX_, ty, tx, U0);
   lds8(s, SC_, ty, tx, Un);
-  eval_dir(U0, g, 0, e0);
-  eval_dir(Un, g, 0, e1);
   put_rec(s, SR0, ty, tx, e0);
   put_rec(s, SR1, ty, tx, e1);
   __syncthreads();
@@ -374,15 +456,24 @@ __global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MSta
   get_rec(s, SR0, ty, txr, en);
   lds8(s, SX_, ty, txr, Un);
   line_outer(L, 4, +1, en, Un, e0, U0);
-  acc_fvs(PB_, L, g.rdx, lx);
-  if (outX) finish(g, dt, U0, PB_, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn);
+  acc_fvs(PB_, L, rdx, lxr);
+  if (outX) {
+    double w[NV];
+    own(1, w);
+    finish(g, dt, w, PB_, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn);
+  }
   __syncthreads();
 
   // d: vertical lines through Y and C.  Y: FVS in y over Y(l-1), C(l-1), Y,
   // C(l), Y(l+1) -> Y complete.
+  {
+    double w[NV];
+    own(2, w);
+    eval_dir(w, g, 1, e0);
+    own(3, w);
+    eval_dir(w, g, 1, e1);
+  }
   lds8(s, SC_, ty, tx, Un);
-  eval_dir(U1, g, 1, e0);
-  eval_dir(Un, g, 1, e1);
   put_rec(s, SR0, ty, tx, e0);
   put_rec(s, SR1, ty, tx, e1);
   __syncthreads();
@@ -397,8 +488,12 @@ __global__ __launch_bounds__(PNT) void k_points(Geo g, CState u, CState un, MSta
   get_rec(s, SR0, tyu, tx, en);
   lds8(s, SY_, tyu, tx, Un);
   line_outer(L, 5, +1, en, Un, e0, U1);
-  acc_fvs(PA, L, g.rdy, ly);
-  if (outY) finish(g, dt, U1, PA, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
+  acc_fvs(PA, L, rdy, lyr);
+  if (outY) {
+    double w[NV];
+    own(2, w);
+    finish(g, dt, w, PA, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
+  }
 }
 
 // ------------------------------------------------------ fused cell update
@@ -421,26 +516,31 @@ constexpr int XF = 20;  // exchange fields: directional record (12) + state (8)
 
 // Sensor primitives of one cell from its average: total pressure, v1, v2,
 // B1, B2 (contraction-free, true divisions, as the indicators need).
-__device__ void sensor_prims(const double U[NV], double gamma, double q[5]) {
+// Formed in FP64 (pressure recovery), stored in the compute type.
+template <class R>
+__device__ void sensor_prims(const double U[NV], double gamma, R q[5]) {
 #pragma clang fp contract(off)
-  q[0] = sensor_pressure(U, gamma) + (U[4] * U[4] + U[5] * U[5] + U[6] * U[6]) / 2.0;
-  q[1] = U[1] / U[0];
-  q[2] = U[2] / U[0];
-  q[3] = U[4];
-  q[4] = U[5];
+  q[0] = (R)(sensor_pressure(U, gamma) + (U[4] * U[4] + U[5] * U[5] + U[6] * U[6]) / 2.0);
+  q[1] = (R)(U[1] / U[0]);
+  q[2] = (R)(U[2] / U[0]);
+  q[3] = (R)U[4];
+  q[4] = (R)U[5];
 }
 
 // Indicators from the primitives of the cell (c) and its neighbours
 // l, r (x) and d, u (y): phi1x, phi1y, phi2, phi3.
-__device__ void sensor_from_prims(const double c[5], const double l[5], const double r[5], const double d[5],
-                                  const double u[5], double dx, double dy, double phi[4]) {
+template <class R>
+__device__ void sensor_from_prims(const R c[5], const R l[5], const R r[5], const R d[5], const R u[5], R dx, R dy,
+                                  R phi[4]) {
 #pragma clang fp contract(off)
-  phi[0] = fabs(r[0] - 2.0 * c[0] + l[0]) / fabs(r[0] + 2.0 * c[0] + l[0]);
-  phi[1] = fabs(u[0] - 2.0 * c[0] + d[0]) / fabs(u[0] + 2.0 * c[0] + d[0]);
-  const double dv = (r[1] - l[1]) / (2.0 * dx) + (u[2] - d[2]) / (2.0 * dy);
-  const double cv = (r[2] - l[2]) / (2.0 * dx) - (u[1] - d[1]) / (2.0 * dy);
-  phi[2] = fmax(-dv / sqrt(dv * dv + cv * cv + 1e-40), 0.0);
-  phi[3] = fabs(r[3] - l[3] + u[4] - d[4]) / (fabs(c[3] + c[4]) + 1e-40);
+  // the regulariser 1e-40 underflows to 0 in FP32; 1e-30 keeps it there
+  const R tiny = IsF32<R>::value ? R(1e-30) : R(1e-40);
+  phi[0] = fabs(r[0] - R(2) * c[0] + l[0]) / fabs(r[0] + R(2) * c[0] + l[0]);
+  phi[1] = fabs(u[0] - R(2) * c[0] + d[0]) / fabs(u[0] + R(2) * c[0] + d[0]);
+  const R dv = (r[1] - l[1]) / (R(2) * dx) + (u[2] - d[2]) / (R(2) * dy);
+  const R cv = (r[2] - l[2]) / (R(2) * dx) - (u[1] - d[1]) / (R(2) * dy);
+  phi[2] = fmax(-dv / sqrt(dv * dv + cv * cv + tiny), R(0));
+  phi[3] = fabs(r[3] - l[3] + u[4] - d[4]) / (fabs(c[3] + c[4]) + tiny);
 }
 
 // Nine-point Powell source of cell (i,j), eq. (semi_av_src): weights
@@ -448,19 +548,19 @@ __device__ void sensor_from_prims(const double c[5], const double l[5], const do
 // the one-sided / central differences of eq. (2d_fd) along the cell's rows
 // and columns, Psi at each point.  The centre sample is the limited centre
 // value, read from the buffer the point kernel fills.
-__device__ void cell_source(const Geo& g, CState u, const double* __restrict__ centre, int i, int j,
-                            double S[NV]) {
+template <class R>
+__device__ void cell_source(const Geo& g, CState u, const double* __restrict__ centre, int i, int j, R S[NV]) {
   double C[NV];
   ldA(g, centre, i, j, C);
   // B1, B2 at the nine samples, [a][b] with a along x, b along y
-  double B1[3][3], B2[3][3];
-  auto ldB = [&](int a, int b, double& b1, double& b2) {
+  R B1[3][3], B2[3][3];
+  auto ldB = [&](int a, int b, R& b1, R& b2) {
     long off;
     const double* base;
     long plane;
     if (a == 1 && b == 1) {
-      b1 = C[4];
-      b2 = C[5];
+      b1 = (R)C[4];
+      b2 = (R)C[5];
       return;
     } else if (b == 1) {
       base = u.x, plane = g.sx, off = (long)map_cell(j, g.ny, g.bcy) * g.nxp + map_node(i + a / 2, g.nx, g.bcx);
@@ -470,38 +570,40 @@ __device__ void cell_source(const Geo& g, CState u, const double* __restrict__ c
       base = u.v, plane = g.sv,
       off = (long)map_node(j + b / 2, g.ny, g.bcy) * g.nxp + map_node(i + a / 2, g.nx, g.bcx);
     }
-    b1 = base[4 * plane + off];
-    b2 = base[5 * plane + off];
+    b1 = (R)base[4 * plane + off];
+    b2 = (R)base[5 * plane + off];
   };
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) ldB(a, b, B1[a][b], B2[a][b]);
-  const double wq[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
-  double f[9];
+  const R wq[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+  const R rdx = (R)g.rdx, rdy = (R)g.rdy;
+  R f[9];
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double dx1 = a == 0 ? (-3.0 * B1[0][b] + 4.0 * B1[1][b] - B1[2][b])
-                       : a == 1 ? (B1[2][b] - B1[0][b])
-                                : (B1[0][b] - 4.0 * B1[1][b] + 3.0 * B1[2][b]);
-      const double dy2 = b == 0 ? (-3.0 * B2[a][0] + 4.0 * B2[a][1] - B2[a][2])
-                       : b == 1 ? (B2[a][2] - B2[a][0])
-                                : (B2[a][0] - 4.0 * B2[a][1] + 3.0 * B2[a][2]);
-      f[3 * b + a] = wq[a] * wq[b] * (dx1 * g.rdx + dy2 * g.rdy);
+      const R dx1 = a == 0 ? (R(-3) * B1[0][b] + R(4) * B1[1][b] - B1[2][b])
+                  : a == 1 ? (B1[2][b] - B1[0][b])
+                           : (B1[0][b] - R(4) * B1[1][b] + R(3) * B1[2][b]);
+      const R dy2 = b == 0 ? (R(-3) * B2[a][0] + R(4) * B2[a][1] - B2[a][2])
+                  : b == 1 ? (B2[a][2] - B2[a][0])
+                           : (B2[a][0] - R(4) * B2[a][1] + R(3) * B2[a][2]);
+      f[3 * b + a] = wq[a] * wq[b] * (dx1 * rdx + dy2 * rdy);
     }
 #pragma unroll
-  for (int c = 0; c < NV; ++c) S[c] = 0.0;
+  for (int c = 0; c < NV; ++c) S[c] = R(0);
   // One sample at a time (a rolled loop): the states of all nine are never
   // live together.
 #pragma unroll 1
   for (int q = 0; q < 9; ++q) {
     const int a = q % 3, b = q / 3;
-    double fq = f[0];
+    R fq = f[0];
 #pragma unroll
     for (int r = 1; r < 9; ++r) fq = q == r ? f[r] : fq;
-    double w[NV], P[NV];
+    double w[NV];
+    R P[NV];
     if (q == 4) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) w[c] = C[c];
@@ -527,43 +629,54 @@ __device__ __forceinline__ int clamp_prim(int i, int n) { return i < -3 ? -3 : (
 // Simpson flux over the edge points w0, w1, w2 (Section 2.2), LLF flux of
 // the adjacent averages (eq. 2d_llf_flux) and the sensor blend: returns
 // F^LLF and dF = theta^s (F_simpson - F^LLF).
+template <class R>
 __device__ __forceinline__ void interface_flux(const Geo& g, int dir, const double w0[NV], const double w1[NV],
-                                               const double w2[NV], const DirEval& eL, const double AL[NV],
-                                               const DirEval& eR, const double AR[NV], double ts, double Fl[NV],
-                                               double dF[NV]) {
-  double Fh[NV], F[NV];
+                                               const double w2[NV], const DirEvalT<R>& eL, const double AL[NV],
+                                               const DirEvalT<R>& eR, const double AR[NV], R ts, R Fl[NV],
+                                               R dF[NV]) {
+  R Fh[NV], F[NV];
   flux_dir(w0, g.gm1, dir, Fh);
   flux_dir(w1, g.gm1, dir, F);
 #pragma unroll
-  for (int c = 0; c < NV; ++c) Fh[c] += 4.0 * F[c];
+  for (int c = 0; c < NV; ++c) Fh[c] += R(4) * F[c];
   flux_dir(w2, g.gm1, dir, F);
-  constexpr double sixth = 1.0 / 6.0;
+  constexpr R sixth = R(1.0 / 6.0);
 #pragma unroll
   for (int c = 0; c < NV; ++c) Fh[c] = (Fh[c] + F[c]) * sixth;
-  const double al = alpha_llf(eL, eR, AL, AR);
+  const R al = alpha_llf(eL, eR, AL, AR);
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
-    Fl[c] = 0.5 * (eL.F[c] + eR.F[c] - al * (AR[c] - AL[c]));
-    dF[c] = ts * Fh[c] + (1.0 - ts) * Fl[c] - Fl[c];
+    Fl[c] = R(0.5) * (eL.F[c] + eR.F[c] - al * (R)(AR[c] - AL[c]));
+    dF[c] = ts * Fh[c] + (R(1) - ts) * Fl[c] - Fl[c];
   }
 }
 
-__device__ __forceinline__ double sensor_theta(double kappa, const double* a, const double* b, int dir) {
-  const double p1 = fmax(a[dir], b[dir]), p2 = fmax(a[2], b[2]), p3 = fmax(a[3], b[3]);
-  return exp(-kappa * (p1 * p2 + p3));
+template <class R>
+__device__ __forceinline__ R sensor_theta(R kappa, const R* a, const R* b, int dir) {
+  const R p1 = fmax(a[dir], b[dir]), p2 = fmax(a[2], b[2]), p3 = fmax(a[3], b[3]);
+  return exp_r(-kappa * (p1 * p2 + p3));
 }
 
+template <class R>
 __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __restrict__ centre,
                                                const double* __restrict__ un, double* __restrict__ out,
                                                const double* dtp, double ca, double cb, Counters* cn, int ntx,
                                                int nty) {
   // s_dfx / s_dfy: theta^s (F_simpson - F^LLF) at the x-interface left of /
   // the y-interface below each thread's cell; they give H_L, H_R, H_D, H_U.
-  __shared__ double s_dfx[NV][CBY][CBX];
-  __shared__ double s_dfy[NV][CBY][CBX];
-  __shared__ double s_x[RF][CBY][CBX];  // exchange: primitives, records, F^LLF, Lambda
-  __shared__ double s_ts[2][CBY][CBX];  // theta^s at the two interfaces
-  __shared__ double s_phi[CBY + 1][CBX + 1][4];
+  __shared__ R s_dfx[NV][CBY][CBX];
+  __shared__ R s_dfy[NV][CBY][CBX];
+  __shared__ R s_x[RF][CBY][CBX];  // exchange: primitives, records, F^LLF, Lambda
+  __shared__ R s_ts[2][CBY][CBX];  // theta^s at the two interfaces
+  __shared__ R s_phi[CBY + 1][CBX + 1][4];
+  // Lambda exchange (FP64): the exchange buffer itself for the FP64 stage
+  double (*s_lam)[CBY][CBX];
+  if constexpr (IsF32<R>::value) {
+    __shared__ double lam_buf[4][CBY][CBX];
+    s_lam = lam_buf;
+  } else {
+    s_lam = reinterpret_cast<double (*)[CBY][CBX]>(&s_x[0][0][0]);
+  }
   int bx, by;
   if (!xcd_tile(ntx, nty, bx, by)) return;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * CBX + tx;
@@ -578,10 +691,11 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
   //     onto the exchange buffer
   constexpr int PW = CBX + 3, PH = CBY + 3;
   static_assert(5 * PW * PH <= RF * CBX * CBY, "primitives must fit the exchange buffer");
-  double* prim = &s_x[0][0][0];
+  R* prim = &s_x[0][0][0];
   for (int it = tid; it < PW * PH; it += CNT) {
     const int a = it % PW, b = it / PW;
-    double U[NV], q[5];
+    double U[NV];
+    R q[5];
     ldA(g, u.a, clamp_prim(i0 - 2 + a, g.nx), clamp_prim(j0 - 2 + b, g.ny), U);
     sensor_prims(U, g.gamma, q);
 #pragma unroll
@@ -592,23 +706,24 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
   for (int it = tid; it < (CBX + 1) * (CBY + 1); it += CNT) {
     const int a = it % (CBX + 1), b = it / (CBX + 1);
     const int pc = (b + 1) * PW + (a + 1);
-    double c[5], l[5], r[5], d[5], up[5], ph[4];
+    R c[5], l[5], r[5], d[5], up[5], ph[4];
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
-      const double* pm = prim + m * PW * PH;
+      const R* pm = prim + m * PW * PH;
       c[m] = pm[pc];
       l[m] = pm[pc - 1];
       r[m] = pm[pc + 1];
       d[m] = pm[pc - PW];
       up[m] = pm[pc + PW];
     }
-    sensor_from_prims(c, l, r, d, up, g.dx, g.dy, ph);
+    sensor_from_prims(c, l, r, d, up, (R)g.dx, (R)g.dy, ph);
 #pragma unroll
     for (int q = 0; q < 4; ++q) s_phi[b][a][q] = ph[q];
   }
   __syncthreads();
 
-  double A[NV], G[NV], S[NV];
+  double A[NV], G[NV];
+  R S[NV];
   ldA(g, u.a, i, j, A);
   // 2: nine-point source (before the interfaces: its temporaries and theirs
   //    are never live together)
@@ -619,11 +734,12 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
   // 3: interfaces.  dir 0: the x-interface left of the cell, dir 1: the
   //    y-interface below it.  The cell's own directional evaluation is
   //    shared with the neighbour on the other side through LDS.
+  const R kappa = (R)g.kappa;
 #pragma unroll
   for (int dir = 0; dir < 2; ++dir) {
-    double Fl[NV];
+    R Fl[NV];
     {
-      DirEval eA, eN;
+      DirEvalT<R> eA, eN;
       double AN[NV];
       eval_dir(A, g, dir, eA);
       put_rec(s_x, ty, tx, eA);
@@ -635,7 +751,8 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
       } else {
         eval_dir(AN, g, dir, eN);
       }
-      double w0[NV], w1[NV], w2[NV], dF[NV];
+      double w0[NV], w1[NV], w2[NV];
+      R dF[NV];
       ldV(g, u.v, i, j, w0);
       if (dir == 0) {
         ldX(g, u.x, i, j, w1);
@@ -644,8 +761,8 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
         ldY(g, u.y, i, j, w1);
         ldV(g, u.v, i + 1, j, w2);
       }
-      const double ts = dir == 0 ? sensor_theta(g.kappa, s_phi[ty + 1][tx], s_phi[ty + 1][tx + 1], 0)
-                                 : sensor_theta(g.kappa, s_phi[ty][tx + 1], s_phi[ty + 1][tx + 1], 1);
+      const R ts = dir == 0 ? sensor_theta(kappa, s_phi[ty + 1][tx], s_phi[ty + 1][tx + 1], 0)
+                            : sensor_theta(kappa, s_phi[ty][tx + 1], s_phi[ty + 1][tx + 1], 1);
       interface_flux(g, dir, w0, w1, w2, eN, AN, eA, A, ts, Fl, dF);
       s_ts[dir][ty][tx] = ts;
 #pragma unroll
@@ -657,24 +774,26 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
     __syncthreads();
     const double lam = dir == 0 ? lx : ly;
 #pragma unroll
-    for (int c = 0; c < NV; ++c) G[c] += lam * (Fl[c] - (dir == 0 ? s_x[c][ty][txr] : s_x[c][tyu][tx]));
+    for (int c = 0; c < NV; ++c) G[c] += lam * (double)(Fl[c] - (dir == 0 ? s_x[c][ty][txr] : s_x[c][tyu][tx]));
     __syncthreads();
   }
   // H_I(c): anti-diffusive updates of the four interfaces
   auto H = [&](int I, int c) -> double {
     switch (I) {
-      case 0: return lx * s_dfx[c][ty][tx];
-      case 1: return -lx * s_dfx[c][ty][txr];
-      case 2: return ly * s_dfy[c][ty][tx];
-      default: return -ly * s_dfy[c][tyu][tx];
+      case 0: return lx * (double)s_dfx[c][ty][tx];
+      case 1: return -lx * (double)s_dfx[c][ty][txr];
+      case 2: return ly * (double)s_dfy[c][ty][tx];
+      default: return -ly * (double)s_dfy[c][tyu][tx];
     }
   };
-  const double tsmin = fmin(fmin(s_ts[0][ty][tx], s_ts[0][ty][txr]), fmin(s_ts[1][ty][tx], s_ts[1][tyu][tx]));
+  const R tsmin = fmin(fmin(s_ts[0][ty][tx], s_ts[0][ty][txr]), fmin(s_ts[1][ty][tx], s_ts[1][tyu][tx]));
 
   // 4: LLF source, sensor blend of the source, flux-limiter steps (1)-(2)
-  double Sl[NV], Allf[NV], Asrc[NV];
+  R Sl[NV];
+  double Allf[NV], Asrc[NV];
   {
-    double P[NV], AN[NV], b;
+    R P[NV];
+    double AN[NV], b;
     ldA(g, u.a, i + 1, j, AN);
     b = AN[4];
     ldA(g, u.a, i - 1, j, AN);
@@ -686,10 +805,10 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
     psi(A, P);
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-      Sl[c] = divb * P[c];
-      S[c] = tsmin * S[c] + (1.0 - tsmin) * Sl[c];
-      Allf[c] = G[c] - dt * Sl[c];
-      Asrc[c] = G[c] - dt * S[c];
+      Sl[c] = (R)divb * P[c];
+      S[c] = tsmin * S[c] + (R(1) - tsmin) * Sl[c];
+      Allf[c] = G[c] - dt * (double)Sl[c];
+      Asrc[c] = G[c] - dt * (double)S[c];
     }
   }
   const double rhoL = Allf[0];
@@ -723,19 +842,20 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
     th = shrink_into_G(th, g.gm1, make);
     make(th, A1);
   }
+  double SL[NV];  // S^Lim
 #pragma unroll
-  for (int c = 0; c < NV; ++c) S[c] = th * S[c] + (1.0 - th) * Sl[c];  // S^Lim
+  for (int c = 0; c < NV; ++c) SL[c] = th * (double)S[c] + (1.0 - th) * (double)Sl[c];
   double Lam[4];
   limiter_box(A1, H, g.gm1, er, ep, Lam, cn, output);
   // 5: unique interface coefficients and the limited update
 #pragma unroll
-  for (int I = 0; I < 4; ++I) s_x[I][ty][tx] = Lam[I];
+  for (int I = 0; I < 4; ++I) s_lam[I][ty][tx] = Lam[I];
   __syncthreads();
   if (!output) return;
-  const double thL = fmin(s_x[1][ty][tx - 1], Lam[0]);
-  const double thR = fmin(Lam[1], s_x[0][ty][tx + 1]);
-  const double thD = fmin(s_x[3][ty - 1][tx], Lam[2]);
-  const double thU = fmin(Lam[3], s_x[2][ty + 1][tx]);
+  const double thL = fmin(s_lam[1][ty][tx - 1], Lam[0]);
+  const double thR = fmin(Lam[1], s_lam[0][ty][tx + 1]);
+  const double thD = fmin(s_lam[3][ty - 1][tx], Lam[2]);
+  const double thU = fmin(Lam[3], s_lam[2][ty + 1][tx]);
   if (thL < 1.0) { count(&cn->n_theta_active); count_min_theta(cn, thL); }
   if (thD < 1.0) { count(&cn->n_theta_active); count_min_theta(cn, thD); }
   if (g.bcx && i == g.nx - 1 && thR < 1.0) { count(&cn->n_theta_active); count_min_theta(cn, thR); }
@@ -743,7 +863,7 @@ __global__ __launch_bounds__(CNT) void k_cells(Geo g, CState u, const double* __
   double An[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c)
-    An[c] = G[c] - dt * S[c] + thL * H(0, c) + thR * H(1, c) + thD * H(2, c) + thU * H(3, c);
+    An[c] = G[c] - dt * SL[c] + thL * H(0, c) + thR * H(1, c) + thD * H(2, c) + thU * H(3, c);
   if (!in_G(An, g.gm1)) count(&cn->n_not_admissible);
   const long off = (long)j * g.nx + i;
   if (ca == 0.0) {
@@ -879,6 +999,7 @@ struct af_mhd_ctx {
   hipStream_t stream;
   std::string err;
   KernelTimer* timer = nullptr;
+  bool f32 = false;  // AF_FLAG_FP32_BULK
   ~af_mhd_ctx() {
     if (timer) {
       for (int q = 0; q < timer->created; ++q) (void)hipEventDestroy(timer->ev[q]);
@@ -899,7 +1020,7 @@ bool valid_params(const af_mhd_params* p) {
   if ((p->bc_x != AF_BC_PERIODIC && p->bc_x != AF_BC_OUTFLOW) ||
       (p->bc_y != AF_BC_PERIODIC && p->bc_y != AF_BC_OUTFLOW))
     return false;
-  return (p->flags & ~(uint32_t)AF_FLAG_KERNEL_TIMING) == 0;
+  return (p->flags & ~(uint32_t)(AF_FLAG_KERNEL_TIMING | AF_FLAG_FP32_BULK)) == 0;
 }
 
 // Fold every recorded pair into the totals (synchronises on the last event).
@@ -1014,14 +1135,22 @@ int run_stage(af_mhd_ctx* c, int k, const af_mhd_state* un, const af_mhd_state* 
   hipEvent_t end;
   hipError_t e = timer_begin(c, KernelTimer::POINTS, &end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
-  k_points<<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(g, u, n, o, c->ws.centre, dt_dev, A[k], B[k], c->ws.cnt,
-                                                       ptx, pty);
+  if (c->f32)
+    k_points<float><<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(g, u, n, o, c->ws.centre, dt_dev, A[k], B[k],
+                                                                c->ws.cnt, ptx, pty);
+  else
+    k_points<double><<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(g, u, n, o, c->ws.centre, dt_dev, A[k], B[k],
+                                                                 c->ws.cnt, ptx, pty);
   e = timer_end(c, end);
   if (e == hipSuccess) e = timer_begin(c, KernelTimer::CELLS, &end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   const int ctx_ = (g.nx + CBX - 4) / (CBX - 3), cty = (g.ny + CBY - 4) / (CBY - 3);
-  k_cells<<<xcd_grid(ctx_, cty), dim3(CBX, CBY), 0, s>>>(g, u, c->ws.centre, n.a, o.a, dt_dev, A[k], B[k],
-                                                         c->ws.cnt, ctx_, cty);
+  if (c->f32)
+    k_cells<float><<<xcd_grid(ctx_, cty), dim3(CBX, CBY), 0, s>>>(g, u, c->ws.centre, n.a, o.a, dt_dev, A[k], B[k],
+                                                                  c->ws.cnt, ctx_, cty);
+  else
+    k_cells<double><<<xcd_grid(ctx_, cty), dim3(CBX, CBY), 0, s>>>(g, u, c->ws.centre, n.a, o.a, dt_dev, A[k],
+                                                                   B[k], c->ws.cnt, ctx_, cty);
   e = timer_end(c, end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   return check_hip(c, "stage launch");
@@ -1069,6 +1198,7 @@ int af_mhd_init(const af_mhd_params* p, void* workspace_dev, size_t workspace_by
   }
   layout(c->g, static_cast<char*>(workspace_dev), &c->ws);
   c->stream = static_cast<hipStream_t>(hip_stream);
+  c->f32 = (p->flags & AF_FLAG_FP32_BULK) != 0;
   if (p->flags & AF_FLAG_KERNEL_TIMING) {
     c->timer = new (std::nothrow) KernelTimer();
     if (!c->timer) {

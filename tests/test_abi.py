@@ -58,8 +58,9 @@ def test_host_side_argument_checks(lib):
     for q in (replace(I.orszag_tang(64), gamma=1.0), replace(I.orszag_tang(64), cfl=0.0),
               replace(I.orszag_tang(64), kappa=-1.0), replace(I.orszag_tang(64), bc_x=7)):
         assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(q))) == 0
-    # flags: only the timing bit is accepted
-    from paper_2506_04857_amd.af_mhd import AF_FLAG_KERNEL_TIMING
+    # flags: only the FP32-bulk and timing bits are accepted
+    from paper_2506_04857_amd.af_mhd import AF_FLAG_FP32_BULK, AF_FLAG_KERNEL_TIMING
     assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), AF_FLAG_KERNEL_TIMING))) == n
+    assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), AF_FLAG_FP32_BULK))) == n
     assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), 1 << 7))) == 0
     assert L.af_mhd_kernel_times(None, None, 0) == AF_EINVAL
