@@ -153,6 +153,61 @@ int af_mhd_kernel_times(af_mhd_ctx* c, af_mhd_kernel_times_t* out, int reset);
 
 void af_mhd_destroy(af_mhd_ctx* c);
 
+/* ------------------------------------------------------------ batches
+ * A batch advances n independent grids together (each with its own
+ * parameters: sizes, domain, gamma, cfl, kappa, boundaries; the flags must
+ * agree).  Per SSP-RK3 step it runs one persistent launch computing every
+ * instance's dt (min(cfl / max wave speed, t_remaining)), then per stage
+ * one persistent launch of the point update over the (instance, tile) work
+ * items of all instances and one of the cell update per cell-tile shape in
+ * use; the step can be captured once into a hipGraph and replayed.  Each
+ * instance's results are bitwise equal to what a single-grid context
+ * computes on it. */
+typedef struct af_mhd_batch af_mhd_batch;
+
+/* Bytes of device workspace for n instances with parameters p[0..n-1]
+ * (two RK scratch states and a centre buffer per instance, dt partials,
+ * counters, launch tables).  0 for invalid parameters or mixed flags. */
+size_t af_mhd_batch_workspace_bytes(const af_mhd_params* p, int n);
+
+/* Create a batch bound to the caller's states[0..n-1] (layout as above;
+ * stepped in place), dt_dev (n device doubles, written every step),
+ * t_remaining_dev (n device doubles read every step, or NULL for no end
+ * time) and workspace (256-byte aligned, af_mhd_batch_workspace_bytes).
+ * All must stay valid until af_mhd_batch_destroy.  tune_table: path of a
+ * text table of cell-tile shapes per size class ("nx ny bc_x bc_y
+ * fp64|fp32 shape" lines); classes missing from it are measured on the
+ * device (a few launches on the first instance of the class, which
+ * compute into the scratch states only) and appended.  NULL: the default
+ * 32x16 tile for every instance.  Synchronises the stream. */
+int af_mhd_batch_init(const af_mhd_params* p, int n, const af_mhd_state* states, double* dt_dev,
+                      const double* t_remaining_dev, void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                      const char* tune_table, af_mhd_batch** out);
+
+/* One SSP-RK3 step of every instance, enqueued on the batch's stream.
+ * use_graph != 0: the first call captures the step into a hipGraph, every
+ * call launches the graph; 0: plain launches. */
+int af_mhd_batch_step(af_mhd_batch* b, int use_graph);
+
+/* Cell-tile shape (threads in x and y) used for instance m. */
+int af_mhd_batch_tile(const af_mhd_batch* b, int m, int* tile_x, int* tile_y);
+
+/* Launch mode of the stage kernels: 1 persistent (about one resident wave
+ * of workgroups stepping through the work items), 0 one work item per
+ * workgroup.  Persistent by default; with a tune table, the faster of the
+ * two on this batch (measured at init on stage-0 launches). */
+int af_mhd_batch_launch_mode(const af_mhd_batch* b, int* persistent);
+
+/* Limiter counters accumulated over all instances since init (the state
+ * statistics fields of out are left zero).  Synchronises the stream. */
+int af_mhd_batch_counters(af_mhd_batch* b, af_mhd_stats_t* out);
+
+void af_mhd_batch_destroy(af_mhd_batch* b);
+
+/* Message of the last error on this batch; with b == NULL, of this
+ * thread's last failed af_mhd_batch_init. */
+const char* af_mhd_batch_last_error(const af_mhd_batch* b);
+
 /* Message of the last error on this context ("" if none); valid until the
  * next call.  With c == NULL: the message of this thread's last failed
  * af_mhd_init. */

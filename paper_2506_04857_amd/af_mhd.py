@@ -93,6 +93,24 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.af_mhd_reset_counters.restype = ctypes.c_int
     L.af_mhd_kernel_times.argtypes = [vp, ctypes.POINTER(af_mhd_kernel_times_t), ctypes.c_int]
     L.af_mhd_kernel_times.restype = ctypes.c_int
+    PA = ctypes.POINTER(af_mhd_params)
+    L.af_mhd_batch_workspace_bytes.argtypes = [PA, ctypes.c_int]
+    L.af_mhd_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.af_mhd_batch_init.argtypes = [PA, ctypes.c_int, S, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_char_p,
+                                    ctypes.POINTER(vp)]
+    L.af_mhd_batch_init.restype = ctypes.c_int
+    L.af_mhd_batch_step.argtypes = [vp, ctypes.c_int]
+    L.af_mhd_batch_step.restype = ctypes.c_int
+    L.af_mhd_batch_tile.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.af_mhd_batch_tile.restype = ctypes.c_int
+    L.af_mhd_batch_launch_mode.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.af_mhd_batch_launch_mode.restype = ctypes.c_int
+    L.af_mhd_batch_counters.argtypes = [vp, ST]
+    L.af_mhd_batch_counters.restype = ctypes.c_int
+    L.af_mhd_batch_destroy.argtypes = [vp]
+    L.af_mhd_batch_destroy.restype = None
+    L.af_mhd_batch_last_error.argtypes = [vp]
+    L.af_mhd_batch_last_error.restype = ctypes.c_char_p
     L.af_mhd_destroy.argtypes = [vp]
     L.af_mhd_destroy.restype = None
     L.af_mhd_last_error.argtypes = [vp]
@@ -193,6 +211,79 @@ class Context:
     def close(self):
         if getattr(self, "_h", None):
             _lib.af_mhd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns one af_mhd_batch: n independent grids stepped together in place.
+    states: list of n device states (tuples of 4 tensors), kept alive here."""
+
+    def __init__(self, probs, states, flags: int = 0, device=None, stream=None, tune_table=None,
+                 t_remaining=None):
+        import torch
+
+        n = len(probs)
+        self.probs = list(probs)
+        self.states = list(states)
+        self.params = (af_mhd_params * n)(*[make_params(p, flags) for p in probs])
+        nbytes = int(_lib.af_mhd_batch_workspace_bytes(self.params, n))
+        if nbytes == 0:
+            raise AfMhdError(AF_EINVAL, "invalid batch parameters")
+        self.device = torch.device(device if device is not None else "cuda")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ws = (self.workspace.data_ptr() + 255) & ~255
+        # a stream of its own by default: hipGraph capture needs a non-null stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.dt_dev = torch.zeros(n, dtype=torch.float64, device=self.device)
+        self.t_rem = None
+        if t_remaining is not None:
+            self.t_rem = torch.as_tensor(t_remaining, dtype=torch.float64).to(self.device).contiguous()
+        torch.cuda.synchronize(self.device)  # the states and tables are ready before the batch's stream runs
+        self._st = (af_mhd_state * n)(*[_state(u) for u in self.states])
+        h = ctypes.c_void_p()
+        rc = _lib.af_mhd_batch_init(self.params, n, self._st, ctypes.c_void_p(self.dt_dev.data_ptr()),
+                                    ctypes.c_void_p(self.t_rem.data_ptr() if self.t_rem is not None else None),
+                                    ctypes.c_void_p(ws), nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                    tune_table.encode() if tune_table else None, ctypes.byref(h))
+        if rc != AF_OK:
+            raise AfMhdError(rc, "af_mhd_batch_init failed: " + _lib.af_mhd_batch_last_error(None).decode())
+        self._h = h
+        self.n = n
+
+    def _check(self, rc: int):
+        if rc != AF_OK:
+            raise AfMhdError(rc, _lib.af_mhd_batch_last_error(self._h).decode())
+        return rc
+
+    def step(self, use_graph: bool = True):
+        """One step of every instance, enqueued on self.stream (synchronise
+        it before reading the states from another stream)."""
+        self._check(_lib.af_mhd_batch_step(self._h, int(bool(use_graph))))
+
+    def tile(self, m: int):
+        tx, ty = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.af_mhd_batch_tile(self._h, m, ctypes.byref(tx), ctypes.byref(ty)))
+        return tx.value, ty.value
+
+    def persistent(self) -> bool:
+        p = ctypes.c_int()
+        self._check(_lib.af_mhd_batch_launch_mode(self._h, ctypes.byref(p)))
+        return bool(p.value)
+
+    def counters(self) -> dict:
+        st = af_mhd_stats_t()
+        self._check(_lib.af_mhd_batch_counters(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.af_mhd_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

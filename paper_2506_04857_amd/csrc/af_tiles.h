@@ -1,0 +1,887 @@
+// af_tiles.h -- the tile bodies of one SSP-RK3 stage of the PP Active Flux
+// scheme for 2D ideal MHD with the Godunov-Powell source (gfx950): the point
+// update (points_tile) and the cell update (cells_tile), the XCD-aware tile
+// order and the reduction helpers.  Shared by the single-grid kernels
+// (af_stage.hip) and the persistent batched kernels (af_batch.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "af_device.h"
+
+namespace afm {
+
+constexpr int BLK = 256;
+
+// XCD-aware tile order: the hardware deals consecutive workgroups round-robin
+// to the 8 XCDs, each with its own L2.  Workgroup b takes logical tile
+// (b % 8) * per + b / 8, so every XCD walks one contiguous band of tiles in
+// row-major order and the halos its tiles share stay in its L2.  Returns
+// false for the padding workgroups of the last band.
+constexpr int NXCD = 8;
+__device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& bx, int& by) {
+  const int n = ntx * nty, per = (n + NXCD - 1) / NXCD;
+  const int b = (int)blockIdx.x;
+  const int t = (b % NXCD) * per + b / NXCD;
+  if (t >= n) return false;
+  bx = t % ntx;
+  by = t / ntx;
+  return true;
+}
+inline int xcd_grid(int ntx, int nty) { return NXCD * ((ntx * nty + NXCD - 1) / NXCD); }
+
+__device__ inline double sensor_pressure(const double U[NV], double gamma) {
+#pragma clang fp contract(off)
+  const double m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+  const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+  return (gamma - 1.0) * (U[7] - m2 / (2.0 * U[0]) - b2 / 2.0);
+}
+
+// ------------------------------------------------------- fused point update
+// One launch updates the point values V, X, Y owned by a tile of
+// (PB-2) x (PB-2) cells (cell (i,j) owns V(i,j), X(i,j), Y(i,j)); the
+// PB x PB threads cover the tile plus a one-cell ring.  The point-value
+// stencils of Section 2.3 run along four families of lines of the
+// half-spaced lattice:
+//   a  horizontal lines through V and Y  (V: FVS in x; Y: central in x)
+//   b  vertical lines through V and X    (V: FVS in y; X: central in y)
+//   c  horizontal lines through X and C  (X: FVS in x)
+//   d  vertical lines through Y and C    (Y: FVS in y)
+// For each family every point is evaluated once (flux, spectral radius,
+// c_f, v_n, sqrt(rho)) and shared through LDS.  FVS in direction n at a
+// point with line neighbours w0..w4 (offsets -h, -h/2, 0, h/2, h):
+//   R = D+F+ + D-F- = [F0 - 4F1 + 4F3 - F4 + alpha (w0 - 4w1 + 6w2 - 4w3 + w4)] / (2h)
+//   alpha = max spectral radius over the five, div part (B0 - 4B1 + 4B3 - B4)/(2h).
+// Central direction: R = (F(up) - F(dn))/h, div part (B(up) - B(dn))/h.
+// The first-order LLF state uses the four neighbours of the point (the
+// line neighbours at +-h for FVS directions, at +-h/2 for the central one).
+constexpr int PB = 16, PNT = PB * PB;
+constexpr int RF = 12;  // record: F[8], sr, cf, vn, sq
+
+template <int W, int H, class R>
+__device__ __forceinline__ void put_rec(R (*s)[H][W], int ty, int tx, const DirEvalT<R>& e) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) s[c][ty][tx] = e.F[c];
+  s[8][ty][tx] = e.sr;
+  s[9][ty][tx] = e.cf;
+  s[10][ty][tx] = e.vn;
+  s[11][ty][tx] = e.sq;
+}
+template <int W, int H, class R>
+__device__ __forceinline__ void get_rec(R (*s)[H][W], int ty, int tx, DirEvalT<R>& e) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) e.F[c] = s[c][ty][tx];
+  e.sr = s[8][ty][tx];
+  e.cf = s[9][ty][tx];
+  e.vn = s[10][ty][tx];
+  e.sq = s[11][ty][tx];
+}
+
+template <class R>
+__device__ __forceinline__ void put_rec(R (*s)[PB][PB], int base, int ty, int tx, const DirEvalT<R>& e) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) s[base + c][ty][tx] = e.F[c];
+  s[base + 8][ty][tx] = e.sr;
+  s[base + 9][ty][tx] = e.cf;
+  s[base + 10][ty][tx] = e.vn;
+  s[base + 11][ty][tx] = e.sq;
+}
+template <class R>
+__device__ __forceinline__ void get_rec(R (*s)[PB][PB], int base, int ty, int tx, DirEvalT<R>& e) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) e.F[c] = s[base + c][ty][tx];
+  e.sr = s[base + 8][ty][tx];
+  e.cf = s[base + 9][ty][tx];
+  e.vn = s[base + 10][ty][tx];
+  e.sq = s[base + 11][ty][tx];
+}
+
+// Incremental FVS along a line (own point e0/U0 at offset 0).  Outer
+// neighbours (offsets -h, +h) are also the LLF neighbours; inner ones
+// (-h/2, +h/2) enter the FVS sums only.  R = (SF + alpha SW)/(2h).
+template <class R>
+struct LineAcc {
+  R SF[NV], SW[NV], G[NV];
+  R alpha, dB, jl;
+};
+
+template <class R>
+__device__ __forceinline__ void line_begin(LineAcc<R>& L, const DirEvalT<R>& e0, const R U0[NV]) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    L.SF[c] = R(0);
+    L.SW[c] = R(6) * U0[c];
+    L.G[c] = R(0);
+  }
+  L.alpha = e0.sr;
+  L.dB = R(0);
+  L.jl = R(0);
+}
+
+// side = -1 for the neighbour at -h (left/below), +1 at +h.
+template <class R>
+__device__ __forceinline__ void line_outer(LineAcc<R>& L, int bn, int side, const DirEvalT<R>& e, const R U[NV],
+                                           const DirEvalT<R>& e0, const R U0[NV]) {
+  L.alpha = fmax(L.alpha, e.sr);
+  const R al = side < 0 ? alpha_llf(e, e0, U, U0) : alpha_llf(e0, e, U0, U);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    L.SF[c] -= side * e.F[c];
+    L.SW[c] += U[c];
+    // F^LLF(U0, U) for side +1, -F^LLF(U, U0) for side -1
+    L.G[c] += side < 0 ? R(-0.5) * (e.F[c] + e0.F[c] - al * (U0[c] - U[c]))
+                       : R(0.5) * (e0.F[c] + e.F[c] - al * (U[c] - U0[c]));
+  }
+  L.dB -= side * U[bn];
+  L.jl += side * U[bn];
+}
+
+template <class R>
+__device__ __forceinline__ void line_inner(LineAcc<R>& L, int bn, int side, const DirEvalT<R>& e, const R U[NV]) {
+  L.alpha = fmax(L.alpha, e.sr);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    L.SF[c] += side * R(4) * e.F[c];
+    L.SW[c] -= R(4) * U[c];
+  }
+  L.dB += side * R(4) * U[bn];
+}
+
+// Point accumulators: high-order RHS h = -R_x - R_y with the div part, and
+// the LLF update l = -dt/dx G_x - dt/dy G_y with its div part.
+template <class R>
+struct PointAcc {
+  R h[NV], l[NV];
+  R divh, divl;
+};
+
+template <class R>
+__device__ __forceinline__ void acc_fvs(PointAcc<R>& P, const LineAcc<R>& L, R rh, R lam) {
+  const R s = R(0.5) * rh;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    P.h[c] -= (L.SF[c] + L.alpha * L.SW[c]) * s;
+    P.l[c] -= lam * L.G[c];
+  }
+  P.divh += L.dB * s;
+  P.divl += L.jl * s;
+}
+
+// Central direction across a face point: neighbours dn/up at -h/2, +h/2;
+// they are also its LLF neighbours.
+template <class R>
+__device__ __forceinline__ void acc_central(PointAcc<R>& P, int bn, R rh, R lam, const DirEvalT<R>& ed,
+                                            const R dn[NV], const DirEvalT<R>& e0, const R U0[NV],
+                                            const DirEvalT<R>& eu, const R up[NV]) {
+  const R ad = alpha_llf(ed, e0, dn, U0), au = alpha_llf(e0, eu, U0, up);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    P.h[c] -= (eu.F[c] - ed.F[c]) * rh;
+    const R G = R(0.5) * (e0.F[c] + eu.F[c] - au * (up[c] - U0[c])) - R(0.5) * (ed.F[c] + e0.F[c] - ad * (U0[c] - dn[c]));
+    P.l[c] -= lam * G;
+  }
+  P.divh += (up[bn] - dn[bn]) * rh;
+  P.divl += R(0.5) * rh * (up[bn] - dn[bn]);
+}
+
+template <class R>
+__device__ __forceinline__ void acc_zero(PointAcc<R>& P) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) P.h[c] = P.l[c] = R(0);
+  P.divh = P.divl = R(0);
+}
+
+// High-order and LLF states from the accumulators (the right-hand sides in
+// the compute type, the states in FP64), scaling limiter, SSP combination,
+// store.
+template <class R>
+__device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[NV], const PointAcc<R>& P,
+                                      double ca, double cb, const double* __restrict__ un, double* __restrict__ out,
+                                      long plane, long off, Counters* cn) {
+  double UH[NV], UL[NV], W[NV];
+  R Ps[NV];
+  psi(U0, Ps);
+  if constexpr (IsF32<R>::value) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      UH[c] = U0[c] + dt * (double)(P.h[c] - P.divh * Ps[c]);
+      UL[c] = U0[c] + (double)(P.l[c] - (float)dt * P.divl * Ps[c]);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      UH[c] = U0[c] + dt * (P.h[c] - P.divh * Ps[c]);
+      UL[c] = U0[c] + P.l[c] - dt * P.divl * Ps[c];
+    }
+  }
+  if (!in_G(UL, g.gm1)) count(&cn->n_llf_not_admissible);
+  limit_point(UH, UL, g.gm1, W, cn, true);
+  if (!in_G(W, g.gm1)) count(&cn->n_not_admissible);
+  if (ca == 0.0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) out[c * plane + off] = W[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) out[c * plane + off] = ca * un[c * plane + off] + cb * W[c];
+  }
+}
+
+__device__ __forceinline__ int clamp_pt(int i, int np) { return i < -1 ? -1 : (i > np ? np : i); }
+
+// LDS layout of k_points (fields of PB x PB values of the compute type):
+// states of the tile's V, X, Y and centre values, then two directional
+// records.
+constexpr int SV_ = 0, SX_ = 8, SY_ = 16, SC_ = 24, SR0 = 32, SR1 = 32 + RF, SFIELDS = 32 + 2 * RF;
+
+template <class R>
+__device__ __forceinline__ void lds8(R (*s)[PB][PB], int base, int ty, int tx, R U[NV]) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) U[c] = s[base + c][ty][tx];
+}
+template <class R>
+__device__ __forceinline__ void sts8(R (*s)[PB][PB], int base, int ty, int tx, const double U[NV]) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) s[base + c][ty][tx] = (R)U[c];
+}
+
+// One tile of the point update.  R = double: the FP64 stage; R = float:
+// the FP32-bulk stage (LDS holds the compute type; a thread's own states are
+// re-read in FP64 from memory for the evaluations and the FP64
+// accumulation).  s: the caller's LDS, SFIELDS x PB x PB values of R.
+template <class R>
+__device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, MState out,
+                                            double* __restrict__ centre, double dt, double ca, double cb,
+                                            Counters* cn, int bx, int by, R (*s)[PB][PB]) {
+  constexpr bool F32 = IsF32<R>::value;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i0 = bx * (PB - 2) - 1, j0 = by * (PB - 2) - 1;
+  const int i = clamp_pt(i0 + tx, g.nxp), j = clamp_pt(j0 + ty, g.nyp);
+  const bool inner = tx >= 1 && tx < PB - 1 && ty >= 1 && ty < PB - 1;
+  const bool outV = inner && i0 + tx < g.nxp && j0 + ty < g.nyp;
+  const bool outX = inner && i0 + tx < g.nxp && j0 + ty < g.ny;
+  const bool outY = inner && i0 + tx < g.nx && j0 + ty < g.nyp;
+  const double lx = dt * g.rdx, ly = dt * g.rdy;
+  const R rdx = (R)g.rdx, rdy = (R)g.rdy, lxr = (R)lx, lyr = (R)ly;
+  const int txl = tx > 0 ? tx - 1 : tx, txr = tx < PB - 1 ? tx + 1 : tx;
+  const int tyd = ty > 0 ? ty - 1 : ty, tyu = ty < PB - 1 ? ty + 1 : ty;
+
+  // 0: the tile's raw point values into LDS
+  {
+    double w[NV];
+    ldV(g, u.v, i, j, w);
+    sts8(s, SV_, ty, tx, w);
+    ldX(g, u.x, i, j, w);
+    sts8(s, SX_, ty, tx, w);
+    ldY(g, u.y, i, j, w);
+    sts8(s, SY_, ty, tx, w);
+  }
+  __syncthreads();
+  // a thread's own FP64 states (V, X, Y; the centre is kept in C64)
+  double C64[NV];
+  auto own = [&](int which, double U[NV]) {
+    if constexpr (F32) {
+      if (which == 0) ldV(g, u.v, i, j, U);
+      else if (which == 1) ldX(g, u.x, i, j, U);
+      else if (which == 2) ldY(g, u.y, i, j, U);
+      else {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) U[c] = C64[c];
+      }
+    } else {
+      lds8(s, which == 0 ? SV_ : which == 1 ? SX_ : which == 2 ? SY_ : SC_, ty, tx, U);
+    }
+  };
+  // 1: centre values in FP64 (the last column/row's are never used); the
+  //    owner also stores its value for the cell kernel's source term
+  {
+    double A[NV], Uc[NV], f[NV], w[NV], q[NV];
+    ldA(g, u.a, i, j, A);
+    if constexpr (F32) {
+      ldX(g, u.x, i, j, f);
+      ldX(g, u.x, i + 1, j, w);
+      ldY(g, u.y, i, j, Uc);
+      ldY(g, u.y, i, j + 1, q);
+    } else {
+      lds8(s, SX_, ty, tx, f);
+      lds8(s, SX_, ty, txr, w);
+      lds8(s, SY_, ty, tx, Uc);
+      lds8(s, SY_, tyu, tx, q);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) f[c] = -4.0 * ((f[c] + w[c]) + (Uc[c] + q[c]));
+    if constexpr (F32) {
+      ldV(g, u.v, i, j, Uc);
+      ldV(g, u.v, i + 1, j, w);
+    } else {
+      lds8(s, SV_, ty, tx, Uc);
+      lds8(s, SV_, ty, txr, w);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Uc[c] += w[c];
+    if constexpr (F32) {
+      ldV(g, u.v, i, j + 1, q);
+      ldV(g, u.v, i + 1, j + 1, w);
+    } else {
+      lds8(s, SV_, tyu, tx, q);
+      lds8(s, SV_, tyu, txr, w);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
+    const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
+    limit_centre(Uc, A, g.gm1, C64, cn, owner);
+    sts8(s, SC_, ty, tx, C64);
+    if (owner) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C64[c];
+    }
+  }
+  PointAcc<R> PA, PB_;
+  DirEvalT<R> e0, e1, en;
+  R U0[NV], U1[NV], Un[NV];
+  LineAcc<R> L;
+
+  // b: vertical lines through V and X.  V: FVS in y over V(l-1), X(l-1), V,
+  // X(l), V(l+1).  X: central in y between V(k,j) and V(k,j+1).
+  {
+    double w[NV];
+    own(0, w);
+    eval_dir(w, g, 1, e0);
+    own(1, w);
+    eval_dir(w, g, 1, e1);
+  }
+  lds8(s, SV_, ty, tx, U0);
+  lds8(s, SX_, ty, tx, U1);
+  put_rec(s, SR0, ty, tx, e0);
+  put_rec(s, SR1, ty, tx, e1);
+  __syncthreads();
+  acc_zero(PA);  // V
+  acc_zero(PB_); // X
+  line_begin(L, e0, U0);
+  get_rec(s, SR0, tyd, tx, en);
+  lds8(s, SV_, tyd, tx, Un);
+  line_outer(L, 5, -1, en, Un, e0, U0);
+  get_rec(s, SR1, tyd, tx, en);
+  lds8(s, SX_, tyd, tx, Un);
+  line_inner(L, 5, -1, en, Un);
+  line_inner(L, 5, +1, e1, U1);
+  get_rec(s, SR0, tyu, tx, en);
+  lds8(s, SV_, tyu, tx, Un);
+  line_outer(L, 5, +1, en, Un, e0, U0);
+  acc_fvs(PA, L, rdy, lyr);
+  acc_central(PB_, 5, rdy, lyr, e0, U0, e1, U1, en, Un);
+  __syncthreads();
+
+  // a: horizontal lines through V and Y.  V: FVS in x over V(k-1), Y(k-1),
+  // V, Y(k), V(k+1) -> V complete.  Y: central in x between V(i,l), V(i+1,l).
+  {
+    double w[NV];
+    own(0, w);
+    eval_dir(w, g, 0, e0);
+    own(2, w);
+    eval_dir(w, g, 0, e1);
+  }
+  lds8(s, SY_, ty, tx, U1);
+  put_rec(s, SR0, ty, tx, e0);
+  put_rec(s, SR1, ty, tx, e1);
+  __syncthreads();
+  line_begin(L, e0, U0);
+  get_rec(s, SR0, ty, txl, en);
+  lds8(s, SV_, ty, txl, Un);
+  line_outer(L, 4, -1, en, Un, e0, U0);
+  get_rec(s, SR1, ty, txl, en);
+  lds8(s, SY_, ty, txl, Un);
+  line_inner(L, 4, -1, en, Un);
+  line_inner(L, 4, +1, e1, U1);
+  get_rec(s, SR0, ty, txr, en);
+  lds8(s, SV_, ty, txr, Un);
+  line_outer(L, 4, +1, en, Un, e0, U0);
+  acc_fvs(PA, L, rdx, lxr);
+  if (outV) {
+    double w[NV];
+    own(0, w);
+    finish(g, dt, w, PA, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
+  }
+  acc_zero(PA);  // now Y
+  acc_central(PA, 4, rdx, lxr, e0, U0, e1, U1, en, Un);
+  __syncthreads();
+
+  // c: horizontal lines through X and C.  X: FVS in x over X(k-1), C(k-1),
+  // X, C(k), X(k+1) -> X complete.
+  {
+    double w[NV];
+    own(1, w);
+    eval_dir(w, g, 0, e0);
+    own(3, w);
+    eval_dir(w, g, 0, e1);
+  }
+  lds8(s, SX_, ty, tx, U0);
+  lds8(s, SC_, ty, tx, Un);
+  put_rec(s, SR0, ty, tx, e0);
+  put_rec(s, SR1, ty, tx, e1);
+  __syncthreads();
+  line_begin(L, e0, U0);
+  line_inner(L, 4, +1, e1, Un);
+  get_rec(s, SR0, ty, txl, en);
+  lds8(s, SX_, ty, txl, Un);
+  line_outer(L, 4, -1, en, Un, e0, U0);
+  get_rec(s, SR1, ty, txl, en);
+  lds8(s, SC_, ty, txl, Un);
+  line_inner(L, 4, -1, en, Un);
+  get_rec(s, SR0, ty, txr, en);
+  lds8(s, SX_, ty, txr, Un);
+  line_outer(L, 4, +1, en, Un, e0, U0);
+  acc_fvs(PB_, L, rdx, lxr);
+  if (outX) {
+    double w[NV];
+    own(1, w);
+    finish(g, dt, w, PB_, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn);
+  }
+  __syncthreads();
+
+  // d: vertical lines through Y and C.  Y: FVS in y over Y(l-1), C(l-1), Y,
+  // C(l), Y(l+1) -> Y complete.
+  {
+    double w[NV];
+    own(2, w);
+    eval_dir(w, g, 1, e0);
+    own(3, w);
+    eval_dir(w, g, 1, e1);
+  }
+  lds8(s, SC_, ty, tx, Un);
+  put_rec(s, SR0, ty, tx, e0);
+  put_rec(s, SR1, ty, tx, e1);
+  __syncthreads();
+  line_begin(L, e0, U1);
+  line_inner(L, 5, +1, e1, Un);
+  get_rec(s, SR0, tyd, tx, en);
+  lds8(s, SY_, tyd, tx, Un);
+  line_outer(L, 5, -1, en, Un, e0, U1);
+  get_rec(s, SR1, tyd, tx, en);
+  lds8(s, SC_, tyd, tx, Un);
+  line_inner(L, 5, -1, en, Un);
+  get_rec(s, SR0, tyu, tx, en);
+  lds8(s, SY_, tyu, tx, Un);
+  line_outer(L, 5, +1, en, Un, e0, U1);
+  acc_fvs(PA, L, rdy, lyr);
+  if (outY) {
+    double w[NV];
+    own(2, w);
+    finish(g, dt, w, PA, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
+  }
+}
+
+// ------------------------------------------------------ fused cell update
+// One launch computes the cell averages of the stage for a tile of
+// (CBX-3) x (CBY-3) cells; the block's CBX x CBY threads cover the cells
+// whose flux-limiter box is needed plus one trailing row/column whose left
+// and bottom interfaces close the region.  Per thread (cell (i,j)):
+//   1  shock-sensor indicators of the block's cells and one ring (LDS)
+//   2  x-interface at the cell's left: Simpson flux, LLF flux, sensor blend;
+//      exchanged through LDS so each cell has both of its x-interfaces
+//   3  the same for the bottom y-interface
+//   4  nine-point and LLF sources, flux-limiter steps (1)-(2) -> Lambda
+//   5  Lambda exchanged through LDS, unique interface coefficients, and the
+//      limited update in flux form written as
+//        A^new = G - dt S^Lim + sum_I theta_I H_I,
+//      G = A - dt/dx (F^LLF_R - F^LLF_L) - dt/dy (F^LLF_U - F^LLF_D),
+//      H_L = dt/dx (F^s_L - F^LLF_L), H_R = -dt/dx (F^s_R - F^LLF_R), ...
+constexpr int CBX0 = 32, CBY0 = 16;  // the cell tile of the single-grid launch
+
+// Sensor primitives of one cell from its average: total pressure, v1, v2,
+// B1, B2 (contraction-free, true divisions, as the indicators need).
+// Formed in FP64 (pressure recovery), stored in the compute type.
+template <class R>
+__device__ void sensor_prims(const double U[NV], double gamma, R q[5]) {
+#pragma clang fp contract(off)
+  q[0] = (R)(sensor_pressure(U, gamma) + (U[4] * U[4] + U[5] * U[5] + U[6] * U[6]) / 2.0);
+  q[1] = (R)(U[1] / U[0]);
+  q[2] = (R)(U[2] / U[0]);
+  q[3] = (R)U[4];
+  q[4] = (R)U[5];
+}
+
+// Indicators from the primitives of the cell (c) and its neighbours
+// l, r (x) and d, u (y): phi1x, phi1y, phi2, phi3.
+template <class R>
+__device__ void sensor_from_prims(const R c[5], const R l[5], const R r[5], const R d[5], const R u[5], R dx, R dy,
+                                  R phi[4]) {
+#pragma clang fp contract(off)
+  // the regulariser 1e-40 underflows to 0 in FP32; 1e-30 keeps it there
+  const R tiny = IsF32<R>::value ? R(1e-30) : R(1e-40);
+  phi[0] = fabs(r[0] - R(2) * c[0] + l[0]) / fabs(r[0] + R(2) * c[0] + l[0]);
+  phi[1] = fabs(u[0] - R(2) * c[0] + d[0]) / fabs(u[0] + R(2) * c[0] + d[0]);
+  const R dv = (r[1] - l[1]) / (R(2) * dx) + (u[2] - d[2]) / (R(2) * dy);
+  const R cv = (r[2] - l[2]) / (R(2) * dx) - (u[1] - d[1]) / (R(2) * dy);
+  phi[2] = fmax(-dv / sqrt(dv * dv + cv * cv + tiny), R(0));
+  phi[3] = fabs(r[3] - l[3] + u[4] - d[4]) / (fabs(c[3] + c[4]) + tiny);
+}
+
+// Nine-point Powell source of cell (i,j), eq. (semi_av_src): weights
+// (1/6, 2/3, 1/6) per direction, the divergence at each sample point from
+// the one-sided / central differences of eq. (2d_fd) along the cell's rows
+// and columns, Psi at each point.  The centre sample is the limited centre
+// value, read from the buffer the point kernel fills.
+template <class R>
+__device__ void cell_source(const Geo& g, CState u, const double* __restrict__ centre, int i, int j, R S[NV]) {
+  double C[NV];
+  ldA(g, centre, i, j, C);
+  // B1, B2 at the nine samples, [a][b] with a along x, b along y
+  R B1[3][3], B2[3][3];
+  auto ldB = [&](int a, int b, R& b1, R& b2) {
+    long off;
+    const double* base;
+    long plane;
+    if (a == 1 && b == 1) {
+      b1 = (R)C[4];
+      b2 = (R)C[5];
+      return;
+    } else if (b == 1) {
+      base = u.x, plane = g.sx, off = (long)map_cell(j, g.ny, g.bcy) * g.nxp + map_node(i + a / 2, g.nx, g.bcx);
+    } else if (a == 1) {
+      base = u.y, plane = g.sy, off = (long)map_node(j + b / 2, g.ny, g.bcy) * g.nx + map_cell(i, g.nx, g.bcx);
+    } else {
+      base = u.v, plane = g.sv,
+      off = (long)map_node(j + b / 2, g.ny, g.bcy) * g.nxp + map_node(i + a / 2, g.nx, g.bcx);
+    }
+    b1 = (R)base[4 * plane + off];
+    b2 = (R)base[5 * plane + off];
+  };
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ldB(a, b, B1[a][b], B2[a][b]);
+  const R wq[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+  const R rdx = (R)g.rdx, rdy = (R)g.rdy;
+  R f[9];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R dx1 = a == 0 ? (R(-3) * B1[0][b] + R(4) * B1[1][b] - B1[2][b])
+                  : a == 1 ? (B1[2][b] - B1[0][b])
+                           : (B1[0][b] - R(4) * B1[1][b] + R(3) * B1[2][b]);
+      const R dy2 = b == 0 ? (R(-3) * B2[a][0] + R(4) * B2[a][1] - B2[a][2])
+                  : b == 1 ? (B2[a][2] - B2[a][0])
+                           : (B2[a][0] - R(4) * B2[a][1] + R(3) * B2[a][2]);
+      f[3 * b + a] = wq[a] * wq[b] * (dx1 * rdx + dy2 * rdy);
+    }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) S[c] = R(0);
+  // One sample at a time (a rolled loop): the states of all nine are never
+  // live together.
+#pragma unroll 1
+  for (int q = 0; q < 9; ++q) {
+    const int a = q % 3, b = q / 3;
+    R fq = f[0];
+#pragma unroll
+    for (int r = 1; r < 9; ++r) fq = q == r ? f[r] : fq;
+    double w[NV];
+    R P[NV];
+    if (q == 4) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) w[c] = C[c];
+    } else if (b == 1) {
+      ldX(g, u.x, i + a / 2, j, w);
+    } else if (a == 1) {
+      ldY(g, u.y, i, j + b / 2, w);
+    } else {
+      ldV(g, u.v, i + a / 2, j + b / 2, w);
+    }
+    psi(w, P);
+#pragma unroll
+    for (int c = 1; c < NV; ++c) S[c] += fq * P[c];
+  }
+}
+
+__device__ __forceinline__ int clamp_cell(int i, int n) { return i < -2 ? -2 : (i > n + 1 ? n + 1 : i); }
+// Sensor primitives are needed on cells [-3, n+2]: the indicators of the
+// ghost cells -2 and n+1 enter the sensor of the outermost interfaces whose
+// flux-limiter coefficients the boundary cells take.
+__device__ __forceinline__ int clamp_prim(int i, int n) { return i < -3 ? -3 : (i > n + 2 ? n + 2 : i); }
+
+// Simpson flux over the edge points w0, w1, w2 (Section 2.2), LLF flux of
+// the adjacent averages (eq. 2d_llf_flux) and the sensor blend: returns
+// F^LLF and dF = theta^s (F_simpson - F^LLF).
+template <class R>
+__device__ __forceinline__ void interface_flux(const Geo& g, int dir, const double w0[NV], const double w1[NV],
+                                               const double w2[NV], const DirEvalT<R>& eL, const double AL[NV],
+                                               const DirEvalT<R>& eR, const double AR[NV], R ts, R Fl[NV],
+                                               R dF[NV]) {
+  R Fh[NV], F[NV];
+  flux_dir(w0, g.gm1, dir, Fh);
+  flux_dir(w1, g.gm1, dir, F);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Fh[c] += R(4) * F[c];
+  flux_dir(w2, g.gm1, dir, F);
+  constexpr R sixth = R(1.0 / 6.0);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Fh[c] = (Fh[c] + F[c]) * sixth;
+  const R al = alpha_llf(eL, eR, AL, AR);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    Fl[c] = R(0.5) * (eL.F[c] + eR.F[c] - al * (R)(AR[c] - AL[c]));
+    dF[c] = ts * Fh[c] + (R(1) - ts) * Fl[c] - Fl[c];
+  }
+}
+
+template <class R>
+__device__ __forceinline__ R sensor_theta(R kappa, const R* a, const R* b, int dir) {
+  const R p1 = fmax(a[dir], b[dir]), p2 = fmax(a[2], b[2]), p3 = fmax(a[3], b[3]);
+  return exp_r(-kappa * (p1 * p2 + p3));
+}
+
+// LDS of one cell tile.  The Lambda exchange is FP64: for the FP64 stage it
+// reuses the exchange buffer, for the FP32-bulk stage it has its own.
+template <class R, int CBX, int CBY>
+struct CellsLDS {
+  R dfx[NV][CBY][CBX];  // theta^s (F_simpson - F^LLF) at the x-interface left of each cell
+  R dfy[NV][CBY][CBX];  // ... at the y-interface below it; they give H_L, H_R, H_D, H_U
+  R x[RF][CBY][CBX];    // exchange: primitives, records, F^LLF (and Lambda, FP64 stage)
+  R ts[2][CBY][CBX];    // theta^s at the two interfaces
+  R phi[CBY + 1][CBX + 1][4];
+  double lam[IsF32<R>::value ? 4 : 1][CBY][CBX];
+};
+
+// One tile of the cell update: CBX x CBY threads, (CBX-3) x (CBY-3) cells.
+template <class R, int CBX, int CBY>
+__device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double* __restrict__ centre,
+                                           const double* __restrict__ un, double* __restrict__ out, double dt,
+                                           double ca, double cb, Counters* cn, int bx, int by,
+                                           CellsLDS<R, CBX, CBY>& L) {
+  constexpr int CNT = CBX * CBY;
+  auto& s_dfx = L.dfx;
+  auto& s_dfy = L.dfy;
+  auto& s_x = L.x;
+  auto& s_ts = L.ts;
+  auto& s_phi = L.phi;
+  double (*s_lam)[CBY][CBX];
+  if constexpr (IsF32<R>::value) {
+    s_lam = L.lam;
+  } else {
+    s_lam = reinterpret_cast<double (*)[CBY][CBX]>(&L.x[0][0][0]);
+  }
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * CBX + tx;
+  const int i0 = bx * (CBX - 3) - 1, j0 = by * (CBY - 3) - 1;
+  const int i = clamp_cell(i0 + tx, g.nx), j = clamp_cell(j0 + ty, g.ny);
+  const bool output = tx >= 1 && tx < CBX - 2 && ty >= 1 && ty < CBY - 2 && i0 + tx < g.nx && j0 + ty < g.ny;
+  const int txr = tx + 1 < CBX ? tx + 1 : tx, tyu = ty + 1 < CBY ? ty + 1 : ty;
+  const double lx = dt * g.rdx, ly = dt * g.rdy;
+
+  // 1a: sensor primitives on [i0-2, i0+CBX+1) x [j0-2, j0+CBY+1), aliased
+  //     onto the exchange buffer
+  constexpr int PW = CBX + 3, PH = CBY + 3;
+  static_assert(5 * PW * PH <= RF * CBX * CBY, "primitives must fit the exchange buffer");
+  R* prim = &s_x[0][0][0];
+  for (int it = tid; it < PW * PH; it += CNT) {
+    const int a = it % PW, b = it / PW;
+    double U[NV];
+    R q[5];
+    ldA(g, u.a, clamp_prim(i0 - 2 + a, g.nx), clamp_prim(j0 - 2 + b, g.ny), U);
+    sensor_prims(U, g.gamma, q);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) prim[m * PW * PH + it] = q[m];
+  }
+  __syncthreads();
+  // 1b: indicators on [i0-1, i0+CBX) x [j0-1, j0+CBY)
+  for (int it = tid; it < (CBX + 1) * (CBY + 1); it += CNT) {
+    const int a = it % (CBX + 1), b = it / (CBX + 1);
+    const int pc = (b + 1) * PW + (a + 1);
+    R c[5], l[5], r[5], d[5], up[5], ph[4];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const R* pm = prim + m * PW * PH;
+      c[m] = pm[pc];
+      l[m] = pm[pc - 1];
+      r[m] = pm[pc + 1];
+      d[m] = pm[pc - PW];
+      up[m] = pm[pc + PW];
+    }
+    sensor_from_prims(c, l, r, d, up, (R)g.dx, (R)g.dy, ph);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_phi[b][a][q] = ph[q];
+  }
+  __syncthreads();
+
+  double A[NV], G[NV];
+  R S[NV];
+  ldA(g, u.a, i, j, A);
+  // 2: nine-point source (before the interfaces: its temporaries and theirs
+  //    are never live together)
+  cell_source(g, u, centre, i, j, S);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) G[c] = A[c];
+
+  // 3: interfaces.  dir 0: the x-interface left of the cell, dir 1: the
+  //    y-interface below it.  The cell's own directional evaluation is
+  //    shared with the neighbour on the other side through LDS.
+  const R kappa = (R)g.kappa;
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    R Fl[NV];
+    {
+      DirEvalT<R> eA, eN;
+      double AN[NV];
+      eval_dir(A, g, dir, eA);
+      put_rec(s_x, ty, tx, eA);
+      __syncthreads();
+      const int nx_ = dir == 0 ? tx - 1 : tx, ny_ = dir == 0 ? ty : ty - 1;
+      if (dir == 0) ldA(g, u.a, i - 1, j, AN); else ldA(g, u.a, i, j - 1, AN);
+      if ((dir == 0 ? tx : ty) > 0) {
+        get_rec(s_x, ny_, nx_, eN);
+      } else {
+        eval_dir(AN, g, dir, eN);
+      }
+      double w0[NV], w1[NV], w2[NV];
+      R dF[NV];
+      ldV(g, u.v, i, j, w0);
+      if (dir == 0) {
+        ldX(g, u.x, i, j, w1);
+        ldV(g, u.v, i, j + 1, w2);
+      } else {
+        ldY(g, u.y, i, j, w1);
+        ldV(g, u.v, i + 1, j, w2);
+      }
+      const R ts = dir == 0 ? sensor_theta(kappa, s_phi[ty + 1][tx], s_phi[ty + 1][tx + 1], 0)
+                            : sensor_theta(kappa, s_phi[ty][tx + 1], s_phi[ty + 1][tx + 1], 1);
+      interface_flux(g, dir, w0, w1, w2, eN, AN, eA, A, ts, Fl, dF);
+      s_ts[dir][ty][tx] = ts;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) (dir == 0 ? s_dfx : s_dfy)[c][ty][tx] = dF[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) s_x[c][ty][tx] = Fl[c];
+    __syncthreads();
+    const double lam = dir == 0 ? lx : ly;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) G[c] += lam * (double)(Fl[c] - (dir == 0 ? s_x[c][ty][txr] : s_x[c][tyu][tx]));
+    __syncthreads();
+  }
+  // H_I(c): anti-diffusive updates of the four interfaces
+  auto H = [&](int I, int c) -> double {
+    switch (I) {
+      case 0: return lx * (double)s_dfx[c][ty][tx];
+      case 1: return -lx * (double)s_dfx[c][ty][txr];
+      case 2: return ly * (double)s_dfy[c][ty][tx];
+      default: return -ly * (double)s_dfy[c][tyu][tx];
+    }
+  };
+  const R tsmin = fmin(fmin(s_ts[0][ty][tx], s_ts[0][ty][txr]), fmin(s_ts[1][ty][tx], s_ts[1][tyu][tx]));
+
+  // 4: LLF source, sensor blend of the source, flux-limiter steps (1)-(2)
+  R Sl[NV];
+  double Allf[NV], Asrc[NV];
+  {
+    R P[NV];
+    double AN[NV], b;
+    ldA(g, u.a, i + 1, j, AN);
+    b = AN[4];
+    ldA(g, u.a, i - 1, j, AN);
+    double divb = (b - AN[4]) * (0.5 * g.rdx);
+    ldA(g, u.a, i, j + 1, AN);
+    b = AN[5];
+    ldA(g, u.a, i, j - 1, AN);
+    divb += (b - AN[5]) * (0.5 * g.rdy);
+    psi(A, P);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      Sl[c] = (R)divb * P[c];
+      S[c] = tsmin * S[c] + (R(1) - tsmin) * Sl[c];
+      Allf[c] = G[c] - dt * (double)Sl[c];
+      Asrc[c] = G[c] - dt * (double)S[c];
+    }
+  }
+  const double rhoL = Allf[0];
+  const bool llf_in = in_G(Allf, g.gm1);
+  if (output && !llf_in) count(&cn->n_llf_not_admissible);
+  const double er = fmin(EPS_FLOOR, rhoL);
+  double ep = EPS_FLOOR, th = 1.0;
+  double A1[NV];
+  if (!(rhoL > 0.0 && p_at_least(Allf, EPS_FLOOR, g.gm1) && p_at_least(Asrc, EPS_FLOOR, g.gm1))) {
+    // step (1) of the flux limiter may act: exact pressures
+    const double pL = pressure(Allf, g.gm1);
+    ep = fmin(EPS_FLOOR, pL);
+    const double psrc = pressure(Asrc, g.gm1);
+    if (psrc < ep) {
+      th = (pL - ep) / (pL - psrc);
+      if (output) count(&cn->n_source_limited);
+    }
+  }
+  auto make = [&](double tt, double* Wt) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Wt[c] = tt * Asrc[c] + (1.0 - tt) * Allf[c];
+  };
+  if (th == 1.0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) A1[c] = Asrc[c];
+  } else {
+    make(th, A1);
+  }
+  if (th > 0.0 && !in_G(A1, g.gm1)) {
+    if (output) count(&cn->n_fallback);
+    th = shrink_into_G(th, g.gm1, make);
+    make(th, A1);
+  }
+  double SL[NV];  // S^Lim
+#pragma unroll
+  for (int c = 0; c < NV; ++c) SL[c] = th * (double)S[c] + (1.0 - th) * (double)Sl[c];
+  double Lam[4];
+  limiter_box(A1, H, g.gm1, er, ep, Lam, cn, output);
+  // 5: unique interface coefficients and the limited update
+#pragma unroll
+  for (int I = 0; I < 4; ++I) s_lam[I][ty][tx] = Lam[I];
+  __syncthreads();
+  if (!output) return;
+  const double thL = fmin(s_lam[1][ty][tx - 1], Lam[0]);
+  const double thR = fmin(Lam[1], s_lam[0][ty][tx + 1]);
+  const double thD = fmin(s_lam[3][ty - 1][tx], Lam[2]);
+  const double thU = fmin(Lam[3], s_lam[2][ty + 1][tx]);
+  if (thL < 1.0) { count(&cn->n_theta_active); count_min_theta(cn, thL); }
+  if (thD < 1.0) { count(&cn->n_theta_active); count_min_theta(cn, thD); }
+  if (g.bcx && i == g.nx - 1 && thR < 1.0) { count(&cn->n_theta_active); count_min_theta(cn, thR); }
+  if (g.bcy && j == g.ny - 1 && thU < 1.0) { count(&cn->n_theta_active); count_min_theta(cn, thU); }
+  double An[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c)
+    An[c] = G[c] - dt * SL[c] + thL * H(0, c) + thR * H(1, c) + thD * H(2, c) + thU * H(3, c);
+  if (!in_G(An, g.gm1)) count(&cn->n_not_admissible);
+  const long off = (long)j * g.nx + i;
+  if (ca == 0.0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) out[c * g.sc + off] = An[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) out[c * g.sc + off] = ca * un[c * g.sc + off] + cb * An[c];
+  }
+}
+
+// ------------------------------------------------------------- reductions
+// Max over all DoFs of rho_1/dx + rho_2/dy, two passes (deterministic).
+constexpr int RED_BLOCKS = 1024;
+
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double sh[BLK / 64];
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < BLK / 64; ++w) v = fmax(v, sh[w]);
+    sh[0] = v;
+  }
+  __syncthreads();
+  v = sh[0];
+  __syncthreads();
+  return v;
+}
+
+__device__ __forceinline__ void dof_ptr(const Geo& g, CState u, long t, const double*& base, long& plane, long& off) {
+  if (t < g.sc) { base = u.a; plane = g.sc; off = t; return; }
+  t -= g.sc;
+  if (t < g.sx) { base = u.x; plane = g.sx; off = t; return; }
+  t -= g.sx;
+  if (t < g.sy) { base = u.y; plane = g.sy; off = t; return; }
+  t -= g.sy;
+  base = u.v; plane = g.sv; off = t;
+}
+
+
+}  // namespace afm

@@ -83,8 +83,10 @@ def prim_to_cons(w: np.ndarray, gamma: float) -> np.ndarray:
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(5)
 
 
-def sample(prob: Problem, t: float = 0.0):
-    """Initial (or exact, where the set-up has one) state at time t."""
+def sample(prob: Problem, t: float = 0.0, gl: int = 5):
+    """Initial (or exact, where the set-up has one) state at time t; cell
+    averages by a gl x gl Gauss-Legendre rule (5 unless stated)."""
+    gx, gw = (_GL_X, _GL_W) if gl == 5 else np.polynomial.legendre.leggauss(gl)
     f = prob.prim
     g = prob.gamma
     dx, dy = prob.dx, prob.dy
@@ -98,10 +100,10 @@ def sample(prob: Problem, t: float = 0.0):
 
     # cell averages: 5x5 Gauss-Legendre per cell
     cell = np.zeros((8, prob.ny, prob.nx))
-    for a in range(5):
-        for b in range(5):
-            X, Y = np.meshgrid(xc + 0.5 * dx * _GL_X[a], yc + 0.5 * dy * _GL_X[b])
-            cell += 0.25 * _GL_W[a] * _GL_W[b] * cons_at(X, Y)
+    for a in range(gl):
+        for b in range(gl):
+            X, Y = np.meshgrid(xc + 0.5 * dx * gx[a], yc + 0.5 * dy * gx[b])
+            cell += 0.25 * gw[a] * gw[b] * cons_at(X, Y)
     X, Y = np.meshgrid(xn, yc)
     xface = cons_at(X, Y)
     X, Y = np.meshgrid(xc, yn)
@@ -147,6 +149,30 @@ def orszag_tang(n: int = 512) -> Problem:
 
     return Problem("orszag_tang", n, n, 0.0, 2 * math.pi, 0.0, 2 * math.pi, gm, 0.2, 1.0, PERIODIC, PERIODIC,
                    math.pi, prim)
+
+
+BATCH_SIZES = (64, 96, 128, 192, 256)
+
+
+def batched_orszag_tang(count: int = 256, seed: int = BASE_SEED, sizes=BATCH_SIZES) -> list:
+    """An ensemble of independent periodic Orszag-Tang problems: instance k
+    has nx and ny drawn independently from sizes (generator seed), and each
+    primitive field (rho, v1, v2, v3, B1, B2, B3, p) scaled by 1 + 0.05 z
+    with z ~ N(0, 1) from its own generator (seed + 1 + k); v3 = B3 = 0 stay
+    zero, p stays positive and div B stays zero."""
+    rng = np.random.default_rng(seed)
+    dims = rng.choice(np.asarray(sizes), size=(count, 2))
+    out = []
+    base = orszag_tang(int(dims[0][0]))
+    for k in range(count):
+        z = np.random.default_rng(seed + 1 + k).standard_normal(8)
+        scale = 1.0 + 0.05 * z
+
+        def prim(x, y, t, scale=scale):
+            return base.prim(x, y, t) * scale.reshape(8, *([1] * np.ndim(x)))
+
+        out.append(replace(base, name=f"orszag_tang_batch_{k}", nx=int(dims[k][0]), ny=int(dims[k][1]), prim=prim))
+    return out
 
 
 def orszag_tang_paper(n: int = 400) -> Problem:

@@ -64,3 +64,23 @@ def test_host_side_argument_checks(lib):
     assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), AF_FLAG_FP32_BULK))) == n
     assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), 1 << 7))) == 0
     assert L.af_mhd_kernel_times(None, None, 0) == AF_EINVAL
+
+
+def test_batch_host_side_argument_checks(lib):
+    from paper_2506_04857_amd import inputs as I
+    from paper_2506_04857_amd.af_mhd import AF_EINVAL, AF_FLAG_FP32_BULK, af_mhd_params, make_params, load_library
+    L = load_library(LIB)
+    probs = [I.orszag_tang(64), I.alfven(32).with_size(40, 24), I.blast_lowbeta(16)]
+    P = (af_mhd_params * 3)(*[make_params(p) for p in probs])
+    n = L.af_mhd_batch_workspace_bytes(P, 3)
+    # two scratch states and a centre buffer per instance at least
+    need = sum(8 * 8 * (3 * p.nx * p.ny + (p.nxp * p.ny + p.nx * p.nyp + p.nxp * p.nyp) * 2) for p in probs)
+    assert n >= need
+    assert L.af_mhd_batch_workspace_bytes(P, 0) == 0
+    mixed = (af_mhd_params * 2)(make_params(probs[0]), make_params(probs[1], AF_FLAG_FP32_BULK))
+    assert L.af_mhd_batch_workspace_bytes(mixed, 2) == 0
+    import ctypes
+    h = ctypes.c_void_p()
+    assert L.af_mhd_batch_init(P, 3, None, None, None, None, 0, None, None, ctypes.byref(h)) == AF_EINVAL
+    assert L.af_mhd_batch_step(None, 1) == AF_EINVAL
+    assert b"bad argument" in L.af_mhd_batch_last_error(None)

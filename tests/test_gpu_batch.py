@@ -1,0 +1,120 @@
+"""Batched ensembles through the C ABI: every instance of a batch (mixed
+sizes, boundaries and gamma, persistent or flat launches, any cell-tile
+shape, plain launches or hipGraph replays) must be bitwise equal to the
+single-grid context's run on that instance, step by step.
+
+Each DoF's arithmetic is the same in both paths and the dt reduction is a
+max (order-independent), so equality is exact."""
+import os
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from paper_2506_04857_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def af():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    from paper_2506_04857_amd import af_mhd
+    return af_mhd
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_problems():
+    return [
+        I.random_smooth(20, 17, seed=3, bc=I.OUTFLOW),
+        I.alfven(32),
+        I.orszag_tang(40).with_size(40, 24),
+        replace(I.random_shock(18, 15, seed=1, bc=I.PERIODIC, field_jump=3.0), kappa=0.0),
+        I.blast_lowbeta(48),
+        replace(I.random_smooth(13, 29, seed=4), bc_y=I.OUTFLOW),
+    ]
+
+
+def single_runs(af, probs, u0s, nsteps, flags):
+    """States and dts of single-grid contexts after 1..nsteps steps."""
+    import torch
+    out = []
+    for prob, u0 in zip(probs, u0s):
+        ctx = af.Context(prob, flags=flags)
+        u = af.to_device(u0)
+        hist = []
+        for _ in range(nsteps):
+            ctx.af_mhd_step(u)
+            torch.cuda.synchronize()
+            hist.append((af.to_host(u), float(ctx.dt_dev.item())))
+        ctx.close()
+        out.append(hist)
+    return out
+
+
+def check_batch(af, probs, nsteps, flags=0, use_graph=True, tune_table=None, force_mode=None):
+    import torch
+    u0s = [I.sample(p) for p in probs]
+    ref = single_runs(af, probs, u0s, nsteps, flags)
+    states = [af.to_device(u) for u in u0s]
+    b = af.Batch(probs, states, flags=flags, tune_table=tune_table)
+    say(f"[batch] n={len(probs)} flags={flags} graph={use_graph} persistent={b.persistent()} "
+        f"tiles={[b.tile(m) for m in range(len(probs))]}")
+    for n in range(nsteps):
+        b.step(use_graph=use_graph)
+        # eager work and a synchronisation between graph replays
+        junk = torch.ones(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert float(junk) == 1000.0
+        dts = b.dt_dev.cpu().numpy()
+        for m in range(len(probs)):
+            got = af.to_host(states[m])
+            want, dt_want = ref[m][n]
+            assert dts[m] == dt_want, f"step {n} instance {m}: dt {dts[m]!r} vs {dt_want!r}"
+            for a, w in zip(got, want):
+                assert np.array_equal(a, w), f"step {n} instance {m} ({probs[m].name}) differs"
+    cnt = b.counters()
+    b.close()
+    return cnt
+
+
+def test_batch_graph_replays_equal_single_grid_runs(af):
+    cnt = check_batch(af, mixed_problems(), 4, use_graph=True)
+    assert cnt["n_not_admissible"] == 0
+
+
+def test_batch_plain_launches_equal_single_grid_runs(af):
+    check_batch(af, mixed_problems(), 2, use_graph=False)
+
+
+def test_batch_fp32_equals_single_grid_fp32(af):
+    check_batch(af, mixed_problems(), 3, flags=af.AF_FLAG_FP32_BULK, use_graph=True)
+
+
+def test_batch_autotune_table(af, tmp_path):
+    path = str(tmp_path / "tiles.txt")
+    probs = mixed_problems()
+    check_batch(af, probs, 2, use_graph=True, tune_table=path)
+    with open(path) as fh:
+        lines = [ln for ln in fh if ln.strip() and not ln.startswith("#")]
+    classes = {(p.nx, p.ny, p.bc_x, p.bc_y) for p in probs}
+    assert len(lines) == len(classes)
+    say("[batch] tune table:\n" + "".join(lines))
+    # a second batch reads the table and measures nothing new
+    check_batch(af, probs, 1, use_graph=True, tune_table=path)
+    with open(path) as fh:
+        assert len([ln for ln in fh if ln.strip() and not ln.startswith("#")]) == len(classes)
+
+
+def test_batch_of_the_orszag_tang_ensemble_recipe(af):
+    # A few instances of the benchmark ensemble (sizes from {64..256}^2,
+    # perturbed fields): batch vs single grid, bitwise, one graph step.
+    probs = I.batched_orszag_tang(6)
+    check_batch(af, probs, 1, use_graph=True)

@@ -260,3 +260,30 @@ def test_flux_limited_run_conserves_mass_exactly(oracle):
         u, _ = oracle.step(p, u, counters=c)
     assert c.n_theta_active > 20 and c.n_fallback == 0
     assert abs(u[0][0].sum() - m0) <= 1e-13 * abs(m0)
+
+
+def test_batched_ensemble_recipe():
+    # The ensemble's instances: sizes from the stated set, fields scaled per
+    # instance by 1 + 0.05 z (z standard normal), v3 = B3 = 0 kept, p > 0,
+    # and the scaled magnetic field still divergence-free (B1 depends on y
+    # only, B2 on x only).
+    probs = I.batched_orszag_tang(16)
+    assert {p.nx for p in probs} | {p.ny for p in probs} <= set(I.BATCH_SIZES)
+    assert len({(p.nx, p.ny) for p in probs}) > 3
+    x, y = np.meshgrid(np.linspace(0, 6, 7), np.linspace(0, 6, 5))
+    base = I.orszag_tang(64).prim(x, y, 0.0)
+    ratios = []
+    for p in probs:
+        w = p.prim(x, y, 0.0)
+        assert np.all(w[3] == 0) and np.all(w[6] == 0) and np.all(w[7] > 0)
+        r = np.where(base != 0, w / np.where(base != 0, base, 1), 1.0)
+        # one factor per field
+        for c in (0, 1, 2, 4, 5, 7):
+            vals = r[c][base[c] != 0]
+            assert np.allclose(vals, vals[0], rtol=1e-12)
+        ratios.append([r[c][base[c] != 0][0] for c in (0, 1, 2, 4, 5, 7)])
+    z = (np.array(ratios) - 1) / 0.05
+    assert abs(z.mean()) < 0.6 and 0.5 < z.std() < 1.5
+    # the same seed gives the same ensemble
+    again = I.batched_orszag_tang(16)
+    assert [(p.nx, p.ny) for p in again] == [(p.nx, p.ny) for p in probs]
