@@ -113,6 +113,76 @@ def timed_steps(ctx, u, steps, stream):
     return ev0.elapsed_time(ev1)
 
 
+TILE_TABLE = os.path.join(ROOT, "paper_2506_04857_amd", "tiles_mi355x.txt")
+
+
+def batched(af, I, args):
+    """The batched Orszag-Tang ensemble: 256 instances of sizes drawn from
+    {64,96,128,192,256}^2 with perturbed fields, all stepped together (one
+    hipGraph per step; cell tiles from the autotuned table), FP64 and
+    FP32-bulk; against the same instances stepped one after another by
+    single-grid contexts."""
+    import shutil
+    import tempfile
+
+    import torch
+    probs = I.batched_orszag_tang(256)
+    u0s = [I.sample(p, gl=2) for p in probs]
+    cells = sum(p.nx * p.ny for p in probs)
+    table = os.path.join(tempfile.mkdtemp(), "tiles.txt")
+    if os.path.exists(TILE_TABLE):
+        shutil.copy(TILE_TABLE, table)
+    res = {}
+    for name, flags in (("fp64", 0), ("fp32", af.AF_FLAG_FP32_BULK)):
+        states = [af.to_device(u) for u in u0s]
+        b = af.Batch(probs, states, flags=flags, tune_table=table)
+        for _ in range(args.warmup):
+            b.step()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(b.stream)
+        for _ in range(args.steps):
+            b.step()
+        ev1.record(b.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        tiles = {}
+        for m in range(len(probs)):
+            key = "%dx%d" % b.tile(m)
+            tiles[key] = tiles.get(key, 0) + 1
+        res[name] = {"value": cells * 3 * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
+                     "persistent": b.persistent(), "tiles": tiles}
+        b.close()
+        del states
+    # the same instances one after another, single-grid contexts, FP64
+    nseq = max(1, min(args.steps, 20))
+    ctxs = [af.Context(p) for p in probs]
+    us = [af.to_device(u) for u in u0s]
+    for c, u in zip(ctxs, us):
+        c.af_mhd_step(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, u in zip(ctxs, us):
+        for _ in range(nseq):
+            c.af_mhd_step(u)
+    torch.cuda.synchronize()
+    seq = cells * 3 * nseq / (time.perf_counter() - t0)
+    for c in ctxs:
+        c.close()
+    with open(table) as fh:
+        tuned = [ln.strip() for ln in fh if ln.strip() and not ln.startswith("#")]
+    if args.save_tile_table:
+        shutil.copy(table, args.save_tile_table)
+    return {"value": res["fp64"]["value"], "unit": UNIT, "instances": len(probs), "cells": cells,
+            "ms_per_step": res["fp64"]["ms_per_step"], "graph": True,
+            "persistent": res["fp64"]["persistent"], "tiles": res["fp64"]["tiles"],
+            "sequential_value": seq, "speedup_vs_sequential": res["fp64"]["value"] / seq,
+            "fp32_bulk": res["fp32"], "fp32_speedup_vs_fp64": res["fp32"]["value"] / res["fp64"]["value"],
+            "size_classes_tuned": len(tuned),
+            "inputs": "256 periodic Orszag-Tang instances, nx, ny from {64,96,128,192,256}, fields x (1 + 0.05 z), "
+                      "2x2 Gauss cell averages"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +191,9 @@ def main():
     ap.add_argument("--workload", default="orszag_tang_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble measurement")
+    ap.add_argument("--save-tile-table", default="", metavar="PATH",
+                    help="write the cell-tile table the batch used (with new measurements) to PATH")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; multi-GPU runs are not supported "
@@ -213,6 +286,8 @@ def main():
                       "l1_rel_vs_fp64": {"rho": l1_rho, "p": l1_p},
                       "compared_after_steps": args.warmup + args.steps},
     }
+    if not args.no_batch:
+        out["batched"] = batched(af, I, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, u0)
     print(json.dumps(out))

@@ -143,6 +143,14 @@ int af_mhd_step(af_mhd_ctx* c, af_mhd_state* u, double t_remaining, double* dt_d
  * when some DoF of u is outside G. */
 int af_mhd_stats(af_mhd_ctx* c, const af_mhd_state* u, af_mhd_stats_t* out);
 
+/* The two discrete divergences the paper records for the Orszag-Tang
+ * example (Section 4) of the state u, written to divb_dev[0..1] (device):
+ *   div1 = sum over cells and the nine quadrature points of |div B| w_a w_b dx dy,
+ *          div B as in the source of eq. (semi_av_src) (limited centre value);
+ *   div2 = sum over cells of |Simpson edge integral of B.n| / 6 * dx dy, as printed.
+ * Enqueued only; summed in a fixed order (bitwise reproducible). */
+int af_mhd_divb(af_mhd_ctx* c, const af_mhd_state* u, double* divb_dev);
+
 /* Reset the counters to zero (asynchronously on the stream). */
 int af_mhd_reset_counters(af_mhd_ctx* c);
 

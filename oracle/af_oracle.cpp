@@ -1167,4 +1167,57 @@ void orc_cell_diagnostics(const orc_params* p, const double* const* u, double* c
     }
 }
 
+// The two discrete divergences recorded for the Orszag-Tang example
+// (Section 4): div1 sums |div B| at the nine points of every cell, with the
+// same derivatives and weights as the source of eq. (semi_av_src) (limited
+// centre values), times dx dy; div2 sums, per cell, one sixth of the
+// absolute Simpson edge integral of B . n (the Gauss-Green form), times
+// dx dy, as printed.
+void orc_divb(const orc_params* p, const double* const* u, double* out2) {
+  const Grid g = make_grid(p);
+  Access acc{g, StateView{u[0], u[1], u[2], u[3]}};
+  CentreField C;
+  C.nx = g.nx;
+  C.ny = g.ny;
+  C.v.resize((size_t)(g.nx + 4) * (g.ny + 4));
+  Counters cc;
+  for (int j = -2; j < g.ny + 2; ++j)
+    for (int i = -2; i < g.nx + 2; ++i) C.v[(size_t)(j + 2) * (g.nx + 4) + (i + 2)] = centre_value(acc, i, j, g.gamma, cc);
+  const double w[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+  auto d3 = [](int at, double u0, double u1, double u2) {
+    if (at == 0) return -3.0 * u0 + 4.0 * u1 - u2;
+    if (at == 1) return u2 - u0;
+    return u0 - 4.0 * u1 + 3.0 * u2;
+  };
+  double div1 = 0.0, div2 = 0.0;
+  for (int j = 0; j < g.ny; ++j)
+    for (int i = 0; i < g.nx; ++i) {
+      Vec S9[3][3];  // [a][b]: a along x, b along y
+      S9[0][0] = acc.V(i, j);
+      S9[1][0] = acc.Y(i, j);
+      S9[2][0] = acc.V(i + 1, j);
+      S9[0][1] = acc.X(i, j);
+      S9[1][1] = C.at(i, j);
+      S9[2][1] = acc.X(i + 1, j);
+      S9[0][2] = acc.V(i, j + 1);
+      S9[1][2] = acc.Y(i, j + 1);
+      S9[2][2] = acc.V(i + 1, j + 1);
+      double cell1 = 0.0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const double dB1 = d3(a, S9[0][b][4], S9[1][b][4], S9[2][b][4]) / g.dx;
+          const double dB2 = d3(b, S9[a][0][5], S9[a][1][5], S9[a][2][5]) / g.dy;
+          cell1 += std::fabs(dB1 + dB2) * w[a] * w[b];
+        }
+      div1 += cell1 * g.dx * g.dy;
+      const double right = S9[2][0][4] + 4.0 * S9[2][1][4] + S9[2][2][4];
+      const double left = S9[0][0][4] + 4.0 * S9[0][1][4] + S9[0][2][4];
+      const double top = S9[0][2][5] + 4.0 * S9[1][2][5] + S9[2][2][5];
+      const double bottom = S9[0][0][5] + 4.0 * S9[1][0][5] + S9[2][0][5];
+      div2 += std::fabs((right - left) + (top - bottom)) / 6.0 * g.dx * g.dy;
+    }
+  out2[0] = div1;
+  out2[1] = div2;
+}
+
 }  // extern "C"

@@ -127,6 +127,7 @@ def lib():
         L.orc_cell_limiter.argtypes = [_D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, _D, _D, _D, ctypes.POINTER(ctypes.c_int64)]
         L.orc_cell_diagnostics.argtypes = [ctypes.POINTER(_Params), _DD, _D, _D, _D]
+        L.orc_divb.argtypes = [ctypes.POINTER(_Params), _DD, _D]
         _lib = L
     return _lib
 
@@ -274,6 +275,14 @@ def cell_diagnostics(prob, u):
     sensor = np.zeros((4, ny, nx))
     lib().orc_cell_diagnostics(ctypes.byref(_params(prob)), _ptrs(u), _ptr(centre), _ptr(source), _ptr(sensor))
     return centre, source, sensor
+
+
+def divb(prob, u):
+    """(div1, div2): the two discrete divergences of Section 4's
+    Orszag-Tang example."""
+    out = np.zeros(2)
+    lib().orc_divb(ctypes.byref(_params(prob)), _ptrs(u), _ptr(out))
+    return float(out[0]), float(out[1])
 
 
 def point_llf(u, left, right, down, up, dt, dx, dy, gamma):

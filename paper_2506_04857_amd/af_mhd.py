@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.af_mhd_stats.restype = ctypes.c_int
     L.af_mhd_reset_counters.argtypes = [vp]
     L.af_mhd_reset_counters.restype = ctypes.c_int
+    L.af_mhd_divb.argtypes = [vp, S, vp]
+    L.af_mhd_divb.restype = ctypes.c_int
     L.af_mhd_kernel_times.argtypes = [vp, ctypes.POINTER(af_mhd_kernel_times_t), ctypes.c_int]
     L.af_mhd_kernel_times.restype = ctypes.c_int
     PA = ctypes.POINTER(af_mhd_params)
@@ -202,6 +204,13 @@ class Context:
 
     def af_mhd_reset_counters(self):
         self._check(_lib.af_mhd_reset_counters(self._h))
+
+    def af_mhd_divb(self, u):
+        """Device tensor (div1, div2) of the state u (enqueued)."""
+        import torch
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        self._check(_lib.af_mhd_divb(self._h, ctypes.byref(_state(u)), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def af_mhd_kernel_times(self, reset: bool = False) -> dict:
         kt = af_mhd_kernel_times_t()

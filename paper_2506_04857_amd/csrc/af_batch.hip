@@ -53,6 +53,8 @@ struct BDt {            // one instance in the dt launch
 };
 
 constexpr int DT_CHUNK = BLK * 16;  // DoFs per dt work item
+constexpr int TUNE_COPIES = 64;     // most copies of one instance's items in a tuning launch
+constexpr int TUNE_ITEMS = 4096;    // tuning launches carry about this many items
 
 // Work item -> instance: binary search over the first-item offsets.
 template <class T>
@@ -231,6 +233,7 @@ struct af_mhd_batch {
   int cls_items[NSHAPE] = {0, 0, 0};
   int cls_n[NSHAPE] = {0, 0, 0};
   BDt* dts = nullptr;
+  BInst* tune = nullptr;                // TUNE_COPIES entries for the autotuner
   int dt_items = 0;
   double* partial = nullptr;
   Counters* cnt = nullptr;
@@ -312,6 +315,7 @@ size_t batch_layout(const af_mhd_params* p, int n, char* base, af_mhd_batch* b) 
   double* partial = reinterpret_cast<double*>(take(sizeof(double) * parts));
   Counters* cnt = reinterpret_cast<Counters*>(take(sizeof(Counters)));
   char* tabs = take(sizeof(BInst) * (size_t)n * 3 * (1 + NSHAPE) + sizeof(BDt) * (size_t)n);
+  char* tune = take(sizeof(BInst) * (size_t)TUNE_COPIES);
   if (b) {
     b->partial = partial;
     b->cnt = cnt;
@@ -325,6 +329,7 @@ size_t batch_layout(const af_mhd_params* p, int n, char* base, af_mhd_batch* b) 
       }
     }
     b->dts = reinterpret_cast<BDt*>(t);
+    b->tune = reinterpret_cast<BInst*>(tune);
   }
   return off;
 }
@@ -460,9 +465,12 @@ std::map<std::string, int> read_table(const char* path) {
   return t;
 }
 
-// Time the cell update of instance m under each shape (stage 0 into the
-// scratch state; the point update runs first so the centre buffer is
-// valid) and return the fastest shape; us[] receives the timings.
+// Throughput of the cell update of instance m under each shape: its work
+// items repeated until a launch carries about TUNE_ITEMS of them (a filled
+// device, as in a batch), computing stage 0 into the instance's scratch
+// state (the copies write identical values); the point update runs first so
+// that the centre buffer is valid.  Returns the fastest shape; us[] gets
+// the time per instance-launch of each shape.
 int tune_instance(af_mhd_batch* b, int m, double us[NSHAPE]) {
   const Geo& g = b->geo[m];
   const af_mhd_state& U = b->user[m];
@@ -477,9 +485,7 @@ int tune_instance(af_mhd_batch* b, int m, double us[NSHAPE]) {
   // a valid dt for the instances first
   kb_dt_partial<<<b->grid_dt, BLK, 0, s>>>(b->dts, b->n, b->dt_items, b->partial);
   kb_dt_final<<<b->n, BLK, 0, s>>>(b->dts, b->partial, nullptr, b->dt);
-  // four scratch entries at the start of the launch tables (which hold at
-  // least 12 entries and are rebuilt after tuning)
-  BInst* dev = b->pts[0];
+  BInst* dev = b->tune;
   r.first = 0;
   r.ntx = point_tiles_x(g);
   hipError_t e = hipMemcpyAsync(dev, &r, sizeof r, hipMemcpyHostToDevice, s);
@@ -494,22 +500,28 @@ int tune_instance(af_mhd_batch* b, int m, double us[NSHAPE]) {
     return -1;
   }
   int best = 0;
-  for (int q = 0; q < NSHAPE; ++q) {
-    r.ntx = cell_tiles_x(g, q);
+  std::vector<BInst> copies;
+  for (int q = 0; q < NSHAPE && e == hipSuccess; ++q) {
     const int items = cell_tiles_x(g, q) * cell_tiles_y(g, q);
-    e = hipMemcpyAsync(dev + 1 + q, &r, sizeof r, hipMemcpyHostToDevice, s);
+    const int reps = std::max(1, std::min(TUNE_COPIES, TUNE_ITEMS / items));
+    copies.assign(reps, r);
+    for (int c = 0; c < reps; ++c) {
+      copies[c].first = c * items;
+      copies[c].ntx = cell_tiles_x(g, q);
+    }
+    e = hipMemcpyAsync(dev, copies.data(), sizeof(BInst) * reps, hipMemcpyHostToDevice, s);
     float best_ms = 1e30f;
     for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
       e = hipEventRecord(e0, s);
-      if (b->f32) launch_cells<float>(false, q, 0, s, dev + 1 + q, 1, items, 0.0, 1.0, b->cnt);
-      else launch_cells<double>(false, q, 0, s, dev + 1 + q, 1, items, 0.0, 1.0, b->cnt);
+      if (b->f32) launch_cells<float>(false, q, 0, s, dev, reps, reps * items, 0.0, 1.0, b->cnt);
+      else launch_cells<double>(false, q, 0, s, dev, reps, reps * items, 0.0, 1.0, b->cnt);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.0f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (rep > 0) best_ms = std::min(best_ms, ms);  // the first launch warms up
     }
-    us[q] = 1e3 * best_ms;
+    us[q] = 1e3 * best_ms / reps;
     if (us[q] < us[best]) best = q;
   }
   (void)hipEventDestroy(e0);

@@ -121,6 +121,88 @@ __global__ __launch_bounds__(BLK) void k_stats_partial(Geo g, CState u, double* 
   if (threadIdx.x < 4) partial[threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
 }
 
+// The two discrete divergences recorded for the Orszag-Tang example
+// (Section 4), per cell, summed in a fixed order (deterministic):
+//   div1: sum over the nine points of |div B| w_a w_b dx dy, with the
+//         derivatives and weights of the source of eq. (semi_av_src) and
+//         the limited centre value;
+//   div2: one sixth of |Simpson edge integral of B . n| dx dy, as printed.
+__global__ __launch_bounds__(BLK) void k_divb_partial(Geo g, CState u, double* partial) {
+  double s1 = 0.0, s2 = 0.0;
+  for (long t = (long)blockIdx.x * BLK + threadIdx.x; t < g.sc; t += (long)gridDim.x * BLK) {
+    const int i = (int)(t % g.nx), j = (int)(t / g.nx);
+    double A[NV], Uc[NV], f[NV], w[NV], q[NV], C[NV];
+    ldA(g, u.a, i, j, A);
+    ldX(g, u.x, i, j, f);
+    ldX(g, u.x, i + 1, j, w);
+    ldY(g, u.y, i, j, Uc);
+    ldY(g, u.y, i, j + 1, q);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) f[c] = -4.0 * ((f[c] + w[c]) + (Uc[c] + q[c]));
+    ldV(g, u.v, i, j, Uc);
+    ldV(g, u.v, i + 1, j, w);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Uc[c] += w[c];
+    ldV(g, u.v, i, j + 1, q);
+    ldV(g, u.v, i + 1, j + 1, w);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
+    limit_centre(Uc, A, g.gm1, C, nullptr, false);
+    double B1[3][3], B2[3][3];  // [a][b]: a along x, b along y
+    auto put = [&](int a, int b, const double* U) {
+      B1[a][b] = U[4];
+      B2[a][b] = U[5];
+    };
+    ldV(g, u.v, i, j, w);         put(0, 0, w);
+    ldY(g, u.y, i, j, w);         put(1, 0, w);
+    ldV(g, u.v, i + 1, j, w);     put(2, 0, w);
+    ldX(g, u.x, i, j, w);         put(0, 1, w);
+    put(1, 1, C);
+    ldX(g, u.x, i + 1, j, w);     put(2, 1, w);
+    ldV(g, u.v, i, j + 1, w);     put(0, 2, w);
+    ldY(g, u.y, i, j + 1, w);     put(1, 2, w);
+    ldV(g, u.v, i + 1, j + 1, w); put(2, 2, w);
+    const double wq[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+    double c1 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double dx1 = a == 0 ? (-3.0 * B1[0][b] + 4.0 * B1[1][b] - B1[2][b])
+                         : a == 1 ? (B1[2][b] - B1[0][b])
+                                  : (B1[0][b] - 4.0 * B1[1][b] + 3.0 * B1[2][b]);
+        const double dy2 = b == 0 ? (-3.0 * B2[a][0] + 4.0 * B2[a][1] - B2[a][2])
+                         : b == 1 ? (B2[a][2] - B2[a][0])
+                                  : (B2[a][0] - 4.0 * B2[a][1] + 3.0 * B2[a][2]);
+        c1 += fabs(dx1 * g.rdx + dy2 * g.rdy) * wq[a] * wq[b];
+      }
+    const double right = B1[2][0] + 4.0 * B1[2][1] + B1[2][2], left = B1[0][0] + 4.0 * B1[0][1] + B1[0][2];
+    const double top = B2[0][2] + 4.0 * B2[1][2] + B2[2][2], bottom = B2[0][0] + 4.0 * B2[1][0] + B2[2][0];
+    s1 += c1 * (g.dx * g.dy);
+    s2 += fabs((right - left) + (top - bottom)) * (1.0 / 6.0) * (g.dx * g.dy);
+  }
+  __shared__ double sh[2][BLK];
+  sh[0][threadIdx.x] = s1;
+  sh[1][threadIdx.x] = s2;
+  __syncthreads();
+  for (int st = BLK / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + st];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) partial[threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_divb_final(const double* partial, int nparts, double* out) {
+  if (threadIdx.x < 2) {
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += partial[threadIdx.x * nparts + b];
+    out[threadIdx.x] = s;
+  }
+}
+
 __global__ void k_zero_counters(Counters* cn) {
   if (threadIdx.x == 0) {
     cn->n_llf_not_admissible = cn->n_newton = cn->newton_iters_max = cn->n_fallback = cn->n_not_admissible = 0;
@@ -451,6 +533,16 @@ int af_mhd_stats(af_mhd_ctx* c, const af_mhd_state* u, af_mhd_stats_t* out) {
   out->n_dof_not_admissible = (int64_t)bad;
   c->err.clear();
   return bad > 0.0 ? AF_ENOTADMISSIBLE : AF_OK;
+}
+
+int af_mhd_divb(af_mhd_ctx* c, const af_mhd_state* u, double* divb_dev) {
+  if (!c) return AF_EINVAL;
+  if (!valid_state(u) || !aligned8(divb_dev)) return fail(c, AF_EINVAL, "af_mhd_divb: bad argument");
+  const Geo& g = c->g;
+  const int nb = (int)std::min<long>(RED_BLOCKS, std::max<long>(1, nblocks(g.sc)));
+  k_divb_partial<<<nb, BLK, 0, c->stream>>>(g, cstate(u), c->ws.partial);
+  k_divb_final<<<1, 64, 0, c->stream>>>(c->ws.partial, nb, divb_dev);
+  return check_hip(c, "af_mhd_divb launch");
 }
 
 int af_mhd_kernel_times(af_mhd_ctx* c, af_mhd_kernel_times_t* out, int reset) {

@@ -321,3 +321,23 @@ def test_error_paths(af):
     h = ctypes.c_void_p()
     assert af._lib.af_mhd_init(ctypes.byref(p), ctypes.c_void_p(base), n - 1, None, ctypes.byref(h)) == \
         af.AF_EWORKSPACE
+
+
+@pytest.mark.parametrize("name,make,steps", [
+    ("smooth_20x17_outflow", lambda: I.random_smooth(20, 17, seed=5, bc=I.OUTFLOW), 0),
+    ("orszag_tang_96_after_20_steps", lambda: I.orszag_tang(96), 20),
+])
+def test_divb_diagnostics_match_oracle(af, oracle, name, make, steps):
+    import torch
+    prob = make()
+    u0 = I.sample(prob)
+    for _ in range(steps):
+        u0, _ = oracle.step(prob, u0)
+    ctx = af.Context(prob)
+    out = ctx.af_mhd_divb(af.to_device(u0))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ctx.close()
+    want = oracle.divb(prob, u0)
+    say(f"[parity] divB {name}: gpu {got} oracle {want}")
+    assert got[0] == pytest.approx(want[0], rel=1e-12) and got[1] == pytest.approx(want[1], rel=1e-12)

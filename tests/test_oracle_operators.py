@@ -1,10 +1,12 @@
 """Pins of the oracle's discrete operators (Section 2.1-2.3, Section 3.4):
 exactness on polynomials, closed-form values of the shock sensor."""
 import math
+from dataclasses import replace
 
 import numpy as np
 import pytest
 
+from paper_2506_04857_amd import inputs as I
 from paper_2506_04857_amd.inputs import OUTFLOW, PERIODIC, Problem, prim_to_cons
 
 
@@ -248,3 +250,40 @@ def test_sensor_closed_forms(oracle):
     expect = (2 * dx * dx) / (4 * (1 + xc ** 2) + 2 * dx * dx)
     np.testing.assert_allclose(s[0, :, 1:7], expect[None, 1:7].repeat(8, 0), rtol=1e-11)
     assert np.max(np.abs(s[1])) < 1e-15
+
+
+def _linear_field_state(prob, b1, b2):
+    """A state with rho = 1, v = 0, p = 1 and B = (b1(x, y), b2(x, y), 0)
+    sampled at every DoF (cell averages: the centre value suffices for the
+    linear fields used here, whose averages equal their centre values)."""
+    def prim(x, y, t):
+        one = np.ones_like(x)
+        return np.stack([one, 0 * one, 0 * one, 0 * one, b1(x, y) * one, b2(x, y) * one, 0 * one, one])
+    return I.sample(replace(prob, prim=prim))
+
+
+def test_divb_diagnostics_vanish_for_divergence_free_fields(oracle):
+    # B = (y^2 - y, x^2 - x) (each component independent of its own
+    # direction): both discrete divergences vanish to rounding.
+    prob = replace(I.constant_state(12, bc=I.OUTFLOW), nx=12, ny=10)
+    u = _linear_field_state(prob, lambda x, y: y * y - y, lambda x, y: x * x - x)
+    d1, d2 = oracle.divb(prob, u)
+    assert d1 < 1e-12 and d2 < 1e-12
+
+
+def test_divb_diagnostics_exact_for_a_linear_field(oracle):
+    # B1 = x, B2 = 0: div B = 1 everywhere, and the one-sided / central
+    # differences of each cell are exact on linear data, so div1 is the
+    # domain's area; the printed Gauss-Green form gives, per cell,
+    # (1/6) |6 dx| dx dy, i.e. div2 = dx * area.
+    prob = replace(I.constant_state(12, bc=I.OUTFLOW), nx=12, ny=10, x1=1.5, y1=2.0)
+    u = _linear_field_state(prob, lambda x, y: x, lambda x, y: 0 * x)
+    d1, d2 = oracle.divb(prob, u)
+    area = (prob.x1 - prob.x0) * (prob.y1 - prob.y0)
+    assert d1 == pytest.approx(area, rel=1e-13)
+    assert d2 == pytest.approx(prob.dx * area, rel=1e-13)
+    # the y-direction counterpart
+    u = _linear_field_state(prob, lambda x, y: 0 * x, lambda x, y: -2 * y)
+    d1, d2 = oracle.divb(prob, u)
+    assert d1 == pytest.approx(2 * area, rel=1e-13)
+    assert d2 == pytest.approx(2 * prob.dy * area, rel=1e-13)
