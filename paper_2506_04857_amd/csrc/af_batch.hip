@@ -93,7 +93,7 @@ template <class R, bool PERSIST>
 __global__ __launch_bounds__(PNT, IsF32<R>::value ? 2 : 1) void kb_points(const BInst* __restrict__ I, int n,
                                                                           int items, double ca, double cb,
                                                                           Counters* cn) {
-  __shared__ R s[SFIELDS][PB][PB];
+  __shared__ R s[point_fields<R>()][PB][PB];
   int it, end, step;
   if (!item_range<PERSIST>(items, it, end, step)) return;
   for (; it < end; it += step) {

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(PNT, IsF32<R>::value ? 2 : 1) void k_points(Geo g, 
                                                                          double* __restrict__ centre,
                                                                          const double* dtp, double ca, double cb,
                                                                          Counters* cn, int ntx, int nty) {
-  __shared__ R s[SFIELDS][PB][PB];
+  __shared__ R s[point_fields<R>()][PB][PB];
   int bx, by;
   if (!xcd_tile(ntx, nty, bx, by)) return;
   points_tile<R>(g, u, un, out, centre, *dtp, ca, cb, cn, bx, by, s);

@@ -227,10 +227,15 @@ __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[
 
 __device__ __forceinline__ int clamp_pt(int i, int np) { return i < -1 ? -1 : (i > np ? np : i); }
 
-// LDS layout of k_points (fields of PB x PB values of the compute type):
-// states of the tile's V, X, Y and centre values, then two directional
-// records.
-constexpr int SV_ = 0, SX_ = 8, SY_ = 16, SC_ = 24, SR0 = 32, SR1 = 32 + RF, SFIELDS = 32 + 2 * RF;
+// LDS layout (fields of PB x PB values of the compute type): states of the
+// tile's V, X, Y and centre values, then directional records.  The FP64
+// stage publishes the records of two line families at once (families b and
+// a, then c and d: 4 barriers; 32 + 4 x 12 = 80 fields, exactly the 160 KB
+// a workgroup may use); the FP32-bulk stage one family at a time.
+constexpr int SV_ = 0, SX_ = 8, SY_ = 16, SC_ = 24, SR0 = 32, SR1 = 32 + RF, SR2 = 32 + 2 * RF, SR3 = 32 + 3 * RF;
+// LDS fields of a point tile: four records (FP64 stage) or two (FP32-bulk)
+template <class R>
+constexpr int point_fields() { return IsF32<R>::value ? 32 + 2 * RF : 32 + 4 * RF; }
 
 template <class R>
 __device__ __forceinline__ void lds8(R (*s)[PB][PB], int base, int ty, int tx, R U[NV]) {
@@ -246,9 +251,9 @@ __device__ __forceinline__ void sts8(R (*s)[PB][PB], int base, int ty, int tx, c
 // One tile of the point update.  R = double: the FP64 stage; R = float:
 // the FP32-bulk stage (LDS holds the compute type; a thread's own states are
 // re-read in FP64 from memory for the evaluations and the FP64
-// accumulation).  s: the caller's LDS, SFIELDS x PB x PB values of R.
+// accumulation).  s: the caller's LDS, point_fields<R>() x PB x PB values of R.
 template <class R>
-__device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, MState out,
+__device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un, MState out,
                                             double* __restrict__ centre, double dt, double ca, double cb,
                                             Counters* cn, int bx, int by, R (*s)[PB][PB]) {
   constexpr bool F32 = IsF32<R>::value;
@@ -467,6 +472,245 @@ __device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, M
     own(2, w);
     finish(g, dt, w, PA, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
   }
+}
+
+template <class R>
+__device__ __forceinline__ void points_tile_4(const Geo& g, CState u, CState un, MState out,
+                                            double* __restrict__ centre, double dt, double ca, double cb,
+                                            Counters* cn, int bx, int by, R (*s)[PB][PB]) {
+  constexpr bool F32 = IsF32<R>::value;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i0 = bx * (PB - 2) - 1, j0 = by * (PB - 2) - 1;
+  const int i = clamp_pt(i0 + tx, g.nxp), j = clamp_pt(j0 + ty, g.nyp);
+  const bool inner = tx >= 1 && tx < PB - 1 && ty >= 1 && ty < PB - 1;
+  const bool outV = inner && i0 + tx < g.nxp && j0 + ty < g.nyp;
+  const bool outX = inner && i0 + tx < g.nxp && j0 + ty < g.ny;
+  const bool outY = inner && i0 + tx < g.nx && j0 + ty < g.nyp;
+  const double lx = dt * g.rdx, ly = dt * g.rdy;
+  const R rdx = (R)g.rdx, rdy = (R)g.rdy, lxr = (R)lx, lyr = (R)ly;
+  const int txl = tx > 0 ? tx - 1 : tx, txr = tx < PB - 1 ? tx + 1 : tx;
+  const int tyd = ty > 0 ? ty - 1 : ty, tyu = ty < PB - 1 ? ty + 1 : ty;
+
+  // 0: the tile's raw point values into LDS
+  {
+    double w[NV];
+    ldV(g, u.v, i, j, w);
+    sts8(s, SV_, ty, tx, w);
+    ldX(g, u.x, i, j, w);
+    sts8(s, SX_, ty, tx, w);
+    ldY(g, u.y, i, j, w);
+    sts8(s, SY_, ty, tx, w);
+  }
+  __syncthreads();
+  // a thread's own FP64 states (V, X, Y; the centre is kept in C64)
+  double C64[NV];
+  auto own = [&](int which, double U[NV]) {
+    if constexpr (F32) {
+      if (which == 0) ldV(g, u.v, i, j, U);
+      else if (which == 1) ldX(g, u.x, i, j, U);
+      else if (which == 2) ldY(g, u.y, i, j, U);
+      else {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) U[c] = C64[c];
+      }
+    } else {
+      lds8(s, which == 0 ? SV_ : which == 1 ? SX_ : which == 2 ? SY_ : SC_, ty, tx, U);
+    }
+  };
+  // 1: centre values in FP64 (the last column/row's are never used); the
+  //    owner also stores its value for the cell kernel's source term
+  {
+    double A[NV], Uc[NV], f[NV], w[NV], q[NV];
+    ldA(g, u.a, i, j, A);
+    if constexpr (F32) {
+      ldX(g, u.x, i, j, f);
+      ldX(g, u.x, i + 1, j, w);
+      ldY(g, u.y, i, j, Uc);
+      ldY(g, u.y, i, j + 1, q);
+    } else {
+      lds8(s, SX_, ty, tx, f);
+      lds8(s, SX_, ty, txr, w);
+      lds8(s, SY_, ty, tx, Uc);
+      lds8(s, SY_, tyu, tx, q);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) f[c] = -4.0 * ((f[c] + w[c]) + (Uc[c] + q[c]));
+    if constexpr (F32) {
+      ldV(g, u.v, i, j, Uc);
+      ldV(g, u.v, i + 1, j, w);
+    } else {
+      lds8(s, SV_, ty, tx, Uc);
+      lds8(s, SV_, ty, txr, w);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Uc[c] += w[c];
+    if constexpr (F32) {
+      ldV(g, u.v, i, j + 1, q);
+      ldV(g, u.v, i + 1, j + 1, w);
+    } else {
+      lds8(s, SV_, tyu, tx, q);
+      lds8(s, SV_, tyu, txr, w);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
+    const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
+    limit_centre(Uc, A, g.gm1, C64, cn, owner);
+    sts8(s, SC_, ty, tx, C64);
+    if (owner) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C64[c];
+    }
+  }
+  DirEvalT<R> e0, e1, en;
+  R U0[NV], U1[NV], Un[NV];
+  LineAcc<R> L;
+  // records of families b (SR0: V in y, SR1: X in y) and a (SR2: V in x,
+  // SR3: Y in x)
+  {
+    double w[NV];
+    own(0, w);
+    eval_dir(w, g, 1, e0);
+    put_rec(s, SR0, ty, tx, e0);
+    eval_dir(w, g, 0, e0);
+    put_rec(s, SR2, ty, tx, e0);
+    own(1, w);
+    eval_dir(w, g, 1, e0);
+    put_rec(s, SR1, ty, tx, e0);
+    own(2, w);
+    eval_dir(w, g, 0, e0);
+    put_rec(s, SR3, ty, tx, e0);
+  }
+  __syncthreads();
+  PointAcc<R> PA, PX, PY;
+  // V: FVS in y over V(l-1), X(l-1), V, X(l), V(l+1) (family b), then FVS
+  // in x over V(k-1), Y(k-1), V, Y(k), V(k+1) (family a) -> V complete
+  acc_zero(PA);
+  lds8(s, SV_, ty, tx, U0);
+  get_rec(s, SR0, ty, tx, e0);
+  line_begin(L, e0, U0);
+  get_rec(s, SR0, tyd, tx, en);
+  lds8(s, SV_, tyd, tx, Un);
+  line_outer(L, 5, -1, en, Un, e0, U0);
+  get_rec(s, SR1, tyd, tx, en);
+  lds8(s, SX_, tyd, tx, Un);
+  line_inner(L, 5, -1, en, Un);
+  get_rec(s, SR1, ty, tx, en);
+  lds8(s, SX_, ty, tx, Un);
+  line_inner(L, 5, +1, en, Un);
+  get_rec(s, SR0, tyu, tx, en);
+  lds8(s, SV_, tyu, tx, Un);
+  line_outer(L, 5, +1, en, Un, e0, U0);
+  acc_fvs(PA, L, rdy, lyr);
+  get_rec(s, SR2, ty, tx, e0);
+  line_begin(L, e0, U0);
+  get_rec(s, SR2, ty, txl, en);
+  lds8(s, SV_, ty, txl, Un);
+  line_outer(L, 4, -1, en, Un, e0, U0);
+  get_rec(s, SR3, ty, txl, en);
+  lds8(s, SY_, ty, txl, Un);
+  line_inner(L, 4, -1, en, Un);
+  get_rec(s, SR3, ty, tx, en);
+  lds8(s, SY_, ty, tx, Un);
+  line_inner(L, 4, +1, en, Un);
+  get_rec(s, SR2, ty, txr, en);
+  lds8(s, SV_, ty, txr, Un);
+  line_outer(L, 4, +1, en, Un, e0, U0);
+  acc_fvs(PA, L, rdx, lxr);
+  if (outV) {
+    double w[NV];
+    own(0, w);
+    finish(g, dt, w, PA, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
+  }
+  // X: central in y between V(k,j) and V(k,j+1) (family b)
+  acc_zero(PX);
+  get_rec(s, SR0, ty, tx, e0);
+  lds8(s, SV_, ty, tx, U0);
+  get_rec(s, SR1, ty, tx, e1);
+  lds8(s, SX_, ty, tx, U1);
+  get_rec(s, SR0, tyu, tx, en);
+  lds8(s, SV_, tyu, tx, Un);
+  acc_central(PX, 5, rdy, lyr, e0, U0, e1, U1, en, Un);
+  // Y: central in x between V(i,l) and V(i+1,l) (family a)
+  acc_zero(PY);
+  get_rec(s, SR2, ty, tx, e0);
+  get_rec(s, SR3, ty, tx, e1);
+  lds8(s, SY_, ty, tx, U1);
+  get_rec(s, SR2, ty, txr, en);
+  lds8(s, SV_, ty, txr, Un);
+  acc_central(PY, 4, rdx, lxr, e0, U0, e1, U1, en, Un);
+  __syncthreads();
+  // records of families c (SR0: X in x, SR1: C in x) and d (SR2: Y in y,
+  // SR3: C in y)
+  {
+    double w[NV];
+    own(1, w);
+    eval_dir(w, g, 0, e0);
+    put_rec(s, SR0, ty, tx, e0);
+    own(2, w);
+    eval_dir(w, g, 1, e0);
+    put_rec(s, SR2, ty, tx, e0);
+    own(3, w);
+    eval_dir(w, g, 0, e0);
+    put_rec(s, SR1, ty, tx, e0);
+    eval_dir(w, g, 1, e0);
+    put_rec(s, SR3, ty, tx, e0);
+  }
+  __syncthreads();
+  // X: FVS in x over X(k-1), C(k-1), X, C(k), X(k+1) -> X complete
+  lds8(s, SX_, ty, tx, U0);
+  get_rec(s, SR0, ty, tx, e0);
+  line_begin(L, e0, U0);
+  get_rec(s, SR1, ty, tx, en);
+  lds8(s, SC_, ty, tx, Un);
+  line_inner(L, 4, +1, en, Un);
+  get_rec(s, SR0, ty, txl, en);
+  lds8(s, SX_, ty, txl, Un);
+  line_outer(L, 4, -1, en, Un, e0, U0);
+  get_rec(s, SR1, ty, txl, en);
+  lds8(s, SC_, ty, txl, Un);
+  line_inner(L, 4, -1, en, Un);
+  get_rec(s, SR0, ty, txr, en);
+  lds8(s, SX_, ty, txr, Un);
+  line_outer(L, 4, +1, en, Un, e0, U0);
+  acc_fvs(PX, L, rdx, lxr);
+  if (outX) {
+    double w[NV];
+    own(1, w);
+    finish(g, dt, w, PX, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn);
+  }
+  // Y: FVS in y over Y(l-1), C(l-1), Y, C(l), Y(l+1) -> Y complete
+  lds8(s, SY_, ty, tx, U1);
+  get_rec(s, SR2, ty, tx, e0);
+  line_begin(L, e0, U1);
+  get_rec(s, SR3, ty, tx, en);
+  lds8(s, SC_, ty, tx, Un);
+  line_inner(L, 5, +1, en, Un);
+  get_rec(s, SR2, tyd, tx, en);
+  lds8(s, SY_, tyd, tx, Un);
+  line_outer(L, 5, -1, en, Un, e0, U1);
+  get_rec(s, SR3, tyd, tx, en);
+  lds8(s, SC_, tyd, tx, Un);
+  line_inner(L, 5, -1, en, Un);
+  get_rec(s, SR2, tyu, tx, en);
+  lds8(s, SY_, tyu, tx, Un);
+  line_outer(L, 5, +1, en, Un, e0, U1);
+  acc_fvs(PY, L, rdy, lyr);
+  if (outY) {
+    double w[NV];
+    own(2, w);
+    finish(g, dt, w, PY, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
+  }
+}
+
+// One tile of the point update (see above); the FP64 stage publishes two
+// line families per barrier (4 barriers, 160 KB of LDS), the FP32-bulk
+// stage one family per barrier (8 barriers, 56 KB: two workgroups per CU).
+template <class R>
+__device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, MState out,
+                                            double* __restrict__ centre, double dt, double ca, double cb,
+                                            Counters* cn, int bx, int by, R (*s)[PB][PB]) {
+  if constexpr (IsF32<R>::value) points_tile_8<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
+  else points_tile_4<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
 }
 
 // ------------------------------------------------------ fused cell update
