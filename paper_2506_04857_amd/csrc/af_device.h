@@ -102,9 +102,29 @@ __device__ __forceinline__ bool p_at_least(const double U[NV], double eps, doubl
 template <class R> struct IsF32 { static constexpr bool value = false; };
 template <> struct IsF32<float> { static constexpr bool value = true; };
 
-template <class R> __device__ __forceinline__ R rcp_r(R x) { return R(1) / x; }
+// Reciprocal and square root of the flux evaluations and the LLF viscosity.
+// FP64: the hardware approximations refined by two Newton steps (about one
+// ulp instead of correctly rounded, with much shorter dependency chains);
+// arguments are positive or zero (sqrt(0) = 0), never denormal in practice.
+// FP32: the hardware's one-ulp instructions.  Pressures, the sensor, the
+// limiters and their roots use exact division and sqrt.
+template <class R> __device__ __forceinline__ R rcp_r(R x);
+template <> __device__ __forceinline__ double rcp_r<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
 template <> __device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <class R> __device__ __forceinline__ R sqrt_r(R x) { return sqrt(x); }
+template <class R> __device__ __forceinline__ R sqrt_r(R x);
+template <> __device__ __forceinline__ double sqrt_r<double>(double x) {
+  double r = __builtin_amdgcn_rsq(x);  // 1/sqrt(x)
+  const double h = 0.5 * x;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  double q = x * r;                    // sqrt(x), then one correction
+  q = fma(fma(-q, q, x), 0.5 * r, q);
+  return x > 0.0 ? q : 0.0;
+}
 template <> __device__ __forceinline__ float sqrt_r<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <class R> __device__ __forceinline__ R exp_r(R x) { return exp(x); }
 template <> __device__ __forceinline__ float exp_r<float>(float x) { return __expf(x); }
@@ -134,7 +154,7 @@ __device__ __forceinline__ void prim_r(const double U[NV], double gm1, R& ri, R&
     b2 = (float)b2d;
     p = (float)(gm1 * rp) * ri;
   } else {
-    ri = 1.0 / U[0];
+    ri = rcp_r(U[0]);
     v1 = U[1] * ri;
     v2 = U[2] * ri;
     v3 = U[3] * ri;
