@@ -65,7 +65,7 @@ def measured_traffic(workload: str, kernel: str):
     if kv.get("source_sha256") != source_hash():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch." + kernel])
+        return float(kv["traffic_bytes_per_launch." + kernel + "<double>"])
     except (KeyError, ValueError):
         return None
 
@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble measurement")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched-ensemble measurement (its JSON object), e.g. for profiling it")
     ap.add_argument("--save-tile-table", default="", metavar="PATH",
                     help="write the cell-tile table the batch used (with new measurements) to PATH")
     args = ap.parse_args()
@@ -205,6 +207,10 @@ def main():
 
     from paper_2506_04857_amd import af_mhd as af
     from paper_2506_04857_amd import inputs as I
+
+    if args.batch_only:
+        print(json.dumps({"batched": batched(af, I, args)}))
+        return
 
     prob = I.CONFIGS[args.workload]()
     u0 = I.sample(prob)

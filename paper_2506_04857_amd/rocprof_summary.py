@@ -27,7 +27,12 @@ def _rows(path):
 
 
 def _short(name: str) -> str:
-    return name.replace("(anonymous namespace)::", "").split("(")[0].split("<")[0].strip()
+    """Kernel name without return type, namespaces and arguments; template
+    arguments are kept (k_points<double> and k_points<float> differ)."""
+    n = name.replace("(anonymous namespace)::", "").strip()
+    if n.startswith("void "):
+        n = n[5:]
+    return n.split("(")[0].strip()
 
 
 def kernel_stats(path):
@@ -72,9 +77,9 @@ def main(argv=None):
     b.add_argument("--copy-bytes", type=float, required=True)
     args = ap.parse_args(argv)
     if args.cmd == "kernels":
-        print(f"{'kernel':<24} {'calls':>6} {'avg us':>10} {'min us':>10} {'max us':>10} {'share %':>8}")
+        print(f"{'kernel':<34} {'calls':>6} {'avg us':>10} {'min us':>10} {'max us':>10} {'share %':>8}")
         for k in kernel_stats(args.stats_csv):
-            print(f"{k[0]:<24} {k[1]:>6d} {k[2]:>10.2f} {k[3]:>10.2f} {k[4]:>10.2f} {k[5]:>8.2f}")
+            print(f"{k[0][:34]:<34} {k[1]:>6d} {k[2]:>10.2f} {k[3]:>10.2f} {k[4]:>10.2f} {k[5]:>8.2f}")
         return
     fetch = counter_per_dispatch(args.fetch, "FETCH_SIZE")
     write = counter_per_dispatch(args.write, "WRITE_SIZE")
@@ -90,7 +95,7 @@ def main(argv=None):
     print(f"fetch_scale: {sf:.4f}")
     print(f"write_scale: {sw:.4f}")
     for k in sorted(fetch):
-        if k in write and not k.startswith(("void ", "__amd")):
+        if k in write and not k.startswith("__amd") and "at::native" not in k:
             print(f"fetch_kib_per_dispatch.{k}: {fetch[k]:.1f}")
             print(f"write_kib_per_dispatch.{k}: {write[k]:.1f}")
             print(f"traffic_bytes_per_launch.{k}: {1024.0 * (fetch[k] * sf + write[k] * sw):.0f}")
