@@ -84,3 +84,31 @@ def test_batch_host_side_argument_checks(lib):
     assert L.af_mhd_batch_init(P, 3, None, None, None, None, 0, None, None, ctypes.byref(h)) == AF_EINVAL
     assert L.af_mhd_batch_step(None, 1) == AF_EINVAL
     assert b"bad argument" in L.af_mhd_batch_last_error(None)
+
+
+def test_maximum_sizes(lib):
+    # 65536 cells per direction is the largest grid accepted; the workspace
+    # size is computed without overflow; one more is rejected.
+    from dataclasses import replace
+    from paper_2506_04857_amd import inputs as I
+    from paper_2506_04857_amd.af_mhd import load_library, make_params
+    L = load_library(LIB)
+    big = replace(I.orszag_tang(64), nx=65536, ny=65536)
+    n = L.af_mhd_workspace_bytes(ctypes.byref(make_params(big)))
+    # two RK scratch states and a centre buffer: (2 * 4 + 1) * 8 planes of 65536^2 doubles at least
+    assert n >= 9 * 8 * 8 * 65536 * 65536
+    assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(replace(big, nx=65537)))) == 0
+    assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(replace(big, nx=4, ny=4)))) > 0
+
+
+def test_bench_traffic_is_tied_to_the_kernel_sources():
+    # bench.py reports the committed rocprofv3 traffic only for the kernel
+    # sources it was measured on (their SHA-256 is stored with it).
+    import bench
+    h = bench.source_hash()
+    assert h == bench.source_hash() and len(h) == 64
+    t = bench.measured_traffic("orszag_tang_512", "k_points")
+    with open(bench.TRAFFIC_FILE) as fh:
+        recorded = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("source_sha256")]
+    assert (t is not None) == (recorded == [h])
+    assert bench.measured_traffic("blast_lowbeta_1024", "k_points") is None
