@@ -280,8 +280,14 @@ __device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un,
     sts8(s, SY_, ty, tx, w);
   }
   __syncthreads();
-  // a thread's own FP64 states (V, X, Y; the centre is kept in C64)
+  // a thread's own FP64 states (V, X, Y from memory; for the FP32-bulk
+  // stage the FP64 centre values wait in LDS of their own)
   double C64[NV];
+  double (*c64)[PB][PB] = nullptr;
+  if constexpr (F32) {
+    __shared__ double c64_lds[NV][PB][PB];
+    c64 = c64_lds;
+  }
   auto own = [&](int which, double U[NV]) {
     if constexpr (F32) {
       if (which == 0) ldV(g, u.v, i, j, U);
@@ -289,7 +295,7 @@ __device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un,
       else if (which == 2) ldY(g, u.y, i, j, U);
       else {
 #pragma unroll
-        for (int c = 0; c < NV; ++c) U[c] = C64[c];
+        for (int c = 0; c < NV; ++c) U[c] = c64[c][ty][tx];
       }
     } else {
       lds8(s, which == 0 ? SV_ : which == 1 ? SX_ : which == 2 ? SY_ : SC_, ty, tx, U);
@@ -334,6 +340,10 @@ __device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un,
     const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
     limit_centre(Uc, A, g.gm1, C64, cn, owner);
     sts8(s, SC_, ty, tx, C64);
+    if constexpr (F32) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) c64[c][ty][tx] = C64[c];
+    }
     if (owner) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C64[c];
