@@ -246,6 +246,24 @@ def main():
     t_stage = ms * 1e-3 / stages
     value = cells / t_stage
 
+    # the same steps replayed from a hipGraph (a one-instance batch): what
+    # launch-bound small grids gain
+    import torch
+    gstates = [af.to_device(u0)]
+    gb = af.Batch([prob], gstates)
+    for _ in range(args.warmup):
+        gb.step()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(gb.stream)
+    for _ in range(args.steps):
+        gb.step()
+    e1.record(gb.stream)
+    torch.cuda.synchronize()
+    graph_value = cells / (e0.elapsed_time(e1) * 1e-3 / stages)
+    gb.close()
+    del gstates
+
     # FP32-bulk stage on the same workload, and its difference from the
     # FP64 run after the same number of steps (L1 of rho and p, relative)
     ms32, st32, u32, us32 = run(af.AF_FLAG_FP32_BULK)
@@ -284,6 +302,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": algo, "avg_launch_us": us[dom]},
         "kernels_us": us,
+        "graph_step_value": graph_value,
         "stage_hbm_gbs": BYTES_PER_CELL_STAGE * cells / t_stage / 1e9,
         "admissible": bool(st["admissible"]),
         "fp32_bulk": {"value": value32, "unit": UNIT, "speedup_vs_fp64": value32 / value,

@@ -202,8 +202,9 @@ int af_mhd_batch_tile(const af_mhd_batch* b, int m, int* tile_x, int* tile_y);
 
 /* Launch mode of the stage kernels: 1 persistent (about one resident wave
  * of workgroups stepping through the work items), 0 one work item per
- * workgroup.  Persistent by default; with a tune table, the faster of the
- * two on this batch (measured at init on stage-0 launches). */
+ * workgroup.  One item per workgroup by default (the persistent loop costs
+ * the cell kernel registers); with a tune table, the faster of the two on
+ * this batch (measured at init on stage-0 launches). */
 int af_mhd_batch_launch_mode(const af_mhd_batch* b, int* persistent);
 
 /* Limiter counters accumulated over all instances since init (the state

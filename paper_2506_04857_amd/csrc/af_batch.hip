@@ -52,7 +52,7 @@ struct BDt {            // one instance in the dt launch
   double cfl;
 };
 
-constexpr int DT_CHUNK = BLK * 16;  // DoFs per dt work item
+constexpr int DT_CHUNK = BLK * 4;   // DoFs per dt work item
 constexpr int TUNE_COPIES = 64;     // most copies of one instance's items in a tuning launch
 constexpr int TUNE_ITEMS = 4096;    // tuning launches carry about this many items
 
@@ -238,7 +238,7 @@ struct af_mhd_batch {
   double* partial = nullptr;
   Counters* cnt = nullptr;
   int grid_points = 0, grid_cells[NSHAPE] = {0, 0, 0}, grid_dt = 0;
-  bool persist = true;                  // persistent or flat stage launches
+  bool persist = false;                 // persistent or flat stage launches
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string err;
