@@ -229,6 +229,21 @@ class Context:
             pass
 
 
+class Solver(Context):
+    """A context that also advances a state to a final time."""
+
+    def run(self, u, t_final: float, max_steps: int = 10 ** 9, t0: float = 0.0):
+        """SSP-RK3 steps on u (in place) until t_final, the last step
+        shortened to land on it.  Reads each dt back (one synchronisation
+        per step).  Returns (time reached, steps taken)."""
+        t, n = float(t0), 0
+        while t < t_final and n < max_steps:
+            self.af_mhd_step(u, t_final - t)
+            t += float(self.dt_dev.item())
+            n += 1
+        return t, n
+
+
 class Batch:
     """Owns one af_mhd_batch: n independent grids stepped together in place.
     states: list of n device states (tuples of 4 tensors), kept alive here."""

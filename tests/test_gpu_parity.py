@@ -341,3 +341,24 @@ def test_divb_diagnostics_match_oracle(af, oracle, name, make, steps):
     want = oracle.divb(prob, u0)
     say(f"[parity] divB {name}: gpu {got} oracle {want}")
     assert got[0] == pytest.approx(want[0], rel=1e-12) and got[1] == pytest.approx(want[1], rel=1e-12)
+
+
+def test_solver_runs_to_the_final_time(af, oracle):
+    # The last step is shortened to land on t_final; the state equals the
+    # oracle's run with the same time steps.
+    prob = I.alfven(16)
+    u0 = I.sample(prob)
+    s = af.Solver(prob)
+    u = af.to_device(u0)
+    t, n = s.run(u, 0.05)
+    import torch
+    torch.cuda.synchronize()
+    got = af.to_host(u)
+    s.close()
+    assert t == pytest.approx(0.05, rel=1e-14) and n > 1
+    ref, tr = u0, 0.0
+    for _ in range(n):
+        ref, d = oracle.step(prob, ref, t_remaining=0.05 - tr)
+        tr += d
+    assert tr == pytest.approx(0.05, rel=1e-14)
+    assert_parity(got, ref, what="solver run")
