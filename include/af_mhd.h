@@ -222,6 +222,59 @@ const char* af_mhd_batch_last_error(const af_mhd_batch* b);
  * af_mhd_init. */
 const char* af_mhd_last_error(const af_mhd_ctx* c);
 
+/* ------------------------------------------------------------ adjoint
+ * Discrete adjoint of one SSP-RK3 stage out = a_k un + b_k FE(uk, dt): the
+ * transposed Jacobian of the stage of Sections 2-3 with dt fixed and every
+ * decision of the positivity limiters (Sections 3.2, 3.3, the remark on the
+ * centre value and the round-off fallback of Section 4) and of the shock
+ * sensor (Section 3.4) frozen as the recorded forward took it.  Within a
+ * decision the derivative is exact: guarded fractions, the density box, the
+ * vertex roots (implicit derivative of the pressure condition along the
+ * ray), the sensor's exp/max terms and the LLF viscosities (largest of the
+ * Lemma's four speeds) are differentiated.  Conventions: max/min ties go to
+ * the first argument, |x| has derivative +1 at 0, sqrt derivative 0 at 0.
+ * FP64 only (params->flags must be 0).  The state layout is the one above.
+ * Work is enqueued on the context's stream; nothing synchronises. */
+typedef struct af_mhd_adj af_mhd_adj;  /* opaque host object */
+
+/* Bytes of one stage's tape (decisions, limiter coefficients and roots,
+ * interface fluxes, sources, centre values), about 110 doubles per cell.
+ * 0 for invalid parameters. */
+size_t af_mhd_adj_tape_bytes(const af_mhd_params* p);
+
+/* Bytes of the adjoint context's device workspace (adjoints of the stage's
+ * intermediate quantities).  0 for invalid parameters. */
+size_t af_mhd_adj_workspace_bytes(const af_mhd_params* p);
+
+/* Create an adjoint context; workspace_dev: caller-owned, 256-byte
+ * aligned, at least af_mhd_adj_workspace_bytes(p), kept until destroy. */
+int af_mhd_adj_init(const af_mhd_params* p, void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                    af_mhd_adj** out);
+
+/* Recording forward stage: writes out = a_k un + b_k FE(uk, dt) (the same
+ * stage as af_mhd_stage, evaluated entity by entity in the paper's order
+ * with IEEE division; equal to it to rounding) and the stage's tape into
+ * tape_dev (caller-owned device buffer, 256-byte aligned, at least
+ * af_mhd_adj_tape_bytes).  out must not alias uk; un is not read for k = 0. */
+int af_mhd_adj_record(af_mhd_adj* c, int k, const af_mhd_state* un, const af_mhd_state* uk, af_mhd_state* out,
+                      const double* dt_dev, void* tape_dev, size_t tape_bytes);
+
+/* Reverse sweep of the recorded stage k with input uk and tape_dev:
+ *   lam_n += a_k lam_out   and   lam_k += b_k (dFE/duk)^T lam_out,
+ * lam_out being the adjoint of the stage output.  The accumulators are
+ * added to (zero them first for a fresh gradient).  For k = 0 (a_0 = 0)
+ * lam_n is not touched and may be NULL or equal to lam_k.  lam_out must not
+ * alias an accumulator.  Sums use device atomics: the result is not
+ * bitwise reproducible run to run (rounding-level differences only). */
+int af_mhd_adj_stage(af_mhd_adj* c, int k, const af_mhd_state* uk, const void* tape_dev, size_t tape_bytes,
+                     const double* dt_dev, const af_mhd_state* lam_out, af_mhd_state* lam_n, af_mhd_state* lam_k);
+
+void af_mhd_adj_destroy(af_mhd_adj* c);
+
+/* Message of the last error on this adjoint context; with c == NULL, of
+ * this thread's last failed af_mhd_adj_init. */
+const char* af_mhd_adj_last_error(const af_mhd_adj* c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,10 +35,83 @@
 #include <omp.h>
 #endif
 
+// ------------------------------------------------------------ scalar type
+// The plain build computes in double.  Built with -DORC_TANGENT=n the same
+// code runs on forward-mode dual numbers that carry n directional
+// derivatives beside each value (the tangent oracle, the reference for the
+// adjoint).  Every decision -- a guard, a max or min, the sign taken by an
+// absolute value, a Newton stopping test -- is taken on the value, so the
+// derivatives are those of the branch the value takes.  Conventions: ties in
+// max and min go to the first argument (std::max / std::min do this), |x| has
+// derivative +1 at x = 0, and sqrt has derivative 0 at 0.
+#ifdef ORC_TANGENT
+namespace tangent {
+constexpr int ND = ORC_TANGENT;
+struct Dual {
+  double v;
+  double d[ND];
+  Dual() : v(0.0) { for (int q = 0; q < ND; ++q) d[q] = 0.0; }
+  Dual(double x) : v(x) { for (int q = 0; q < ND; ++q) d[q] = 0.0; }  // NOLINT: implicit on purpose
+  Dual& operator+=(const Dual& o) { v += o.v; for (int q = 0; q < ND; ++q) d[q] += o.d[q]; return *this; }
+  Dual& operator-=(const Dual& o) { v -= o.v; for (int q = 0; q < ND; ++q) d[q] -= o.d[q]; return *this; }
+};
+inline Dual operator-(const Dual& a) { Dual r; r.v = -a.v; for (int q = 0; q < ND; ++q) r.d[q] = -a.d[q]; return r; }
+inline Dual operator+(const Dual& a, const Dual& b) { Dual r; r.v = a.v + b.v; for (int q = 0; q < ND; ++q) r.d[q] = a.d[q] + b.d[q]; return r; }
+inline Dual operator-(const Dual& a, const Dual& b) { Dual r; r.v = a.v - b.v; for (int q = 0; q < ND; ++q) r.d[q] = a.d[q] - b.d[q]; return r; }
+inline Dual operator*(const Dual& a, const Dual& b) {
+  Dual r;
+  r.v = a.v * b.v;
+  for (int q = 0; q < ND; ++q) r.d[q] = a.d[q] * b.v + a.v * b.d[q];
+  return r;
+}
+inline Dual operator/(const Dual& a, const Dual& b) {
+  Dual r;
+  r.v = a.v / b.v;
+  for (int q = 0; q < ND; ++q) r.d[q] = (a.d[q] - r.v * b.d[q]) / b.v;
+  return r;
+}
+inline Dual operator+(const Dual& a, double b) { return a + Dual(b); }
+inline Dual operator+(double a, const Dual& b) { return Dual(a) + b; }
+inline Dual operator-(const Dual& a, double b) { return a - Dual(b); }
+inline Dual operator-(double a, const Dual& b) { return Dual(a) - b; }
+inline Dual operator*(const Dual& a, double b) { return a * Dual(b); }
+inline Dual operator*(double a, const Dual& b) { return Dual(a) * b; }
+inline Dual operator/(const Dual& a, double b) { return a / Dual(b); }
+inline Dual operator/(double a, const Dual& b) { return Dual(a) / b; }
+inline bool operator<(const Dual& a, const Dual& b) { return a.v < b.v; }
+inline bool operator>(const Dual& a, const Dual& b) { return a.v > b.v; }
+inline bool operator<=(const Dual& a, const Dual& b) { return a.v <= b.v; }
+inline bool operator>=(const Dual& a, const Dual& b) { return a.v >= b.v; }
+inline Dual sqrt(const Dual& a) {
+  Dual r;
+  r.v = std::sqrt(a.v);
+  for (int q = 0; q < ND; ++q) r.d[q] = r.v > 0.0 ? a.d[q] / (2.0 * r.v) : 0.0;
+  return r;
+}
+inline Dual exp(const Dual& a) {
+  Dual r;
+  r.v = std::exp(a.v);
+  for (int q = 0; q < ND; ++q) r.d[q] = a.d[q] * r.v;
+  return r;
+}
+inline Dual fabs(const Dual& a) { return a.v < 0.0 ? -a : a; }
+inline double val(const Dual& a) { return a.v; }
+}  // namespace tangent
+typedef tangent::Dual real;
+using tangent::val;
+#else
+typedef double real;
+inline double val(double x) { return x; }
+#endif
+
 namespace {
 
+using std::exp;
+using std::fabs;
+using std::sqrt;
+
 constexpr int NV = 8;
-typedef std::array<double, NV> Vec;
+typedef std::array<real, NV> Vec;
 
 struct Grid {
   int nx, ny, nxp, nyp, bcx, bcy;  // bc: 0 periodic, 1 outflow
@@ -63,7 +136,7 @@ int node_index(int k, int n, int bc) {
 }
 
 struct StateView {
-  const double *a, *x, *y, *v;
+  const real *a, *x, *y, *v;
 };
 
 struct Access {
@@ -99,20 +172,20 @@ struct Access {
 // Pressure from the conservative variables, Section 1 (EOS of the perfect gas)
 // and the admissible set of Section 3:
 //   p = (gamma-1) (E - |rho v|^2 / (2 rho) - |B|^2 / 2).
-double pressure(const Vec& U, double gamma) {
-  const double m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
-  const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+real pressure(const Vec& U, double gamma) {
+  const real m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+  const real b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
   return (gamma - 1.0) * (U[7] - m2 / (2.0 * U[0]) - b2 / 2.0);
 }
 
 // Physical fluxes F1 (dir 0) and F2 (dir 1), Section 1.
 Vec flux(const Vec& U, double gamma, int dir) {
-  const double rho = U[0];
-  const double v1 = U[1] / rho, v2 = U[2] / rho, v3 = U[3] / rho;
-  const double B1 = U[4], B2 = U[5], B3 = U[6], E = U[7];
-  const double p = pressure(U, gamma);
-  const double pt = p + (B1 * B1 + B2 * B2 + B3 * B3) / 2.0;
-  const double vB = v1 * B1 + v2 * B2 + v3 * B3;
+  const real rho = U[0];
+  const real v1 = U[1] / rho, v2 = U[2] / rho, v3 = U[3] / rho;
+  const real B1 = U[4], B2 = U[5], B3 = U[6], E = U[7];
+  const real p = pressure(U, gamma);
+  const real pt = p + (B1 * B1 + B2 * B2 + B3 * B3) / 2.0;
+  const real vB = v1 * B1 + v2 * B2 + v3 * B3;
   Vec F;
   if (dir == 0) {
     F[0] = rho * v1;
@@ -138,7 +211,7 @@ Vec flux(const Vec& U, double gamma, int dir) {
 
 // Godunov-Powell source vector Psi = (0, B, v, v.B), eq. (gp_src).
 Vec psi(const Vec& U) {
-  const double v1 = U[1] / U[0], v2 = U[2] / U[0], v3 = U[3] / U[0];
+  const real v1 = U[1] / U[0], v2 = U[2] / U[0], v3 = U[3] / U[0];
   Vec P;
   P[0] = 0.0;
   P[1] = U[4];
@@ -153,35 +226,35 @@ Vec psi(const Vec& U) {
 
 // Fast magnetosonic speed c_{f,l}, eq. (cf).  A negative inner discriminant
 // (round-off only) is clamped to zero.
-double fast_speed(const Vec& U, double gamma, int dir) {
-  const double rho = U[0];
-  const double c2 = gamma * pressure(U, gamma) / rho;
-  const double b2 = (U[4] * U[4] + U[5] * U[5] + U[6] * U[6]) / rho;
-  const double Bl = U[4 + dir];
-  const double s = c2 + b2;
-  double disc = s * s - 4.0 * c2 * Bl * Bl / rho;
+real fast_speed(const Vec& U, double gamma, int dir) {
+  const real rho = U[0];
+  const real c2 = gamma * pressure(U, gamma) / rho;
+  const real b2 = (U[4] * U[4] + U[5] * U[5] + U[6] * U[6]) / rho;
+  const real Bl = U[4 + dir];
+  const real s = c2 + b2;
+  real disc = s * s - 4.0 * c2 * Bl * Bl / rho;
   if (disc < 0.0) disc = 0.0;
-  return std::sqrt(0.5 * (s + std::sqrt(disc)));
+  return sqrt(0.5 * (s + sqrt(disc)));
 }
 
 // Spectral radius of dF_l/dU: |v_l| + c_{f,l} (Section 2.3).
-double spectral_radius(const Vec& U, double gamma, int dir) {
-  return std::fabs(U[1 + dir] / U[0]) + fast_speed(U, gamma, dir);
+real spectral_radius(const Vec& U, double gamma, int dir) {
+  return fabs(U[1 + dir] / U[0]) + fast_speed(U, gamma, dir);
 }
 
 // alpha_{l,*}(U, Ut) of the Lemma (Wu's bound), Section 3.1.
-double alpha_star(const Vec& U, const Vec& Ut, double gamma, int dir) {
-  const double sa = std::sqrt(U[0]), sb = std::sqrt(Ut[0]);
-  const double va = U[1 + dir] / U[0], vb = Ut[1 + dir] / Ut[0];
-  const double t1 = std::max(std::fabs(va), std::fabs(sa * va + sb * vb) / (sa + sb));
-  const double t2 = std::max(fast_speed(U, gamma, dir), fast_speed(Ut, gamma, dir));
-  const double d1 = U[4] - Ut[4], d2 = U[5] - Ut[5], d3 = U[6] - Ut[6];
-  const double t3 = std::sqrt(d1 * d1 + d2 * d2 + d3 * d3) / (sa + sb);
+real alpha_star(const Vec& U, const Vec& Ut, double gamma, int dir) {
+  const real sa = sqrt(U[0]), sb = sqrt(Ut[0]);
+  const real va = U[1 + dir] / U[0], vb = Ut[1 + dir] / Ut[0];
+  const real t1 = std::max(fabs(va), fabs(sa * va + sb * vb) / (sa + sb));
+  const real t2 = std::max(fast_speed(U, gamma, dir), fast_speed(Ut, gamma, dir));
+  const real d1 = U[4] - Ut[4], d2 = U[5] - Ut[5], d3 = U[6] - Ut[6];
+  const real t3 = sqrt(d1 * d1 + d2 * d2 + d3 * d3) / (sa + sb);
   return t1 + t2 + t3;
 }
 
 // LLF viscosity: the Lemma's lower bound taken with equality.
-double alpha_llf(const Vec& U, const Vec& Ut, double gamma, int dir) {
+real alpha_llf(const Vec& U, const Vec& Ut, double gamma, int dir) {
   return std::max(std::max(spectral_radius(U, gamma, dir), spectral_radius(Ut, gamma, dir)),
                   std::max(alpha_star(U, Ut, gamma, dir), alpha_star(Ut, U, gamma, dir)));
 }
@@ -189,7 +262,7 @@ double alpha_llf(const Vec& U, const Vec& Ut, double gamma, int dir) {
 // LLF numerical flux, eq. (2d_llf_flux):
 //   F^LLF(U, Ut) = 1/2 [F(U) + F(Ut) - alpha (Ut - U)].
 Vec llf_flux(const Vec& U, const Vec& Ut, double gamma, int dir) {
-  const double al = alpha_llf(U, Ut, gamma, dir);
+  const real al = alpha_llf(U, Ut, gamma, dir);
   const Vec Fa = flux(U, gamma, dir), Fb = flux(Ut, gamma, dir);
   Vec F;
   for (int c = 0; c < NV; ++c) F[c] = 0.5 * (Fa[c] + Fb[c] - al * (Ut[c] - U[c]));
@@ -236,11 +309,11 @@ constexpr double SHRINK = 1e-8;       // round-off fallback step 2^m * 1e-8
 // until the state is in G; theta = 0 (the safe state) otherwise.
 // make(theta) builds the blended state.
 template <class Make>
-double shrink_until_admissible(double theta, double gamma, Make make, Counters& cnt) {
+real shrink_until_admissible(real theta, double gamma, Make make, Counters& cnt) {
   if (in_G(make(theta), gamma) || theta <= 0.0) return theta;
   ++cnt.n_fallback;
   for (int m = 0; m < 10; ++m) {
-    const double t = std::max(theta - std::ldexp(SHRINK, m), 0.0);
+    const real t = std::max<real>(theta - std::ldexp(SHRINK, m), 0.0);
     if (in_G(make(t), gamma)) return t;
   }
   return 0.0;
@@ -252,18 +325,18 @@ double shrink_until_admissible(double theta, double gamma, Make make, Counters& 
 // blends the whole state.  The two fractions are guarded: each applies only
 // when the bound is violated, so its denominator is positive.
 Vec point_scaling_limiter(const Vec& UH, const Vec& UL, double gamma, Counters& cnt) {
-  const double rhoL = UL[0], pL = pressure(UL, gamma);
-  const double eps_rho = std::min(EPS_FLOOR, rhoL);
-  const double eps_p = std::min(EPS_FLOOR, pL);
-  double th1 = 1.0;
+  const real rhoL = UL[0], pL = pressure(UL, gamma);
+  const real eps_rho = std::min<real>(EPS_FLOOR, rhoL);
+  const real eps_p = std::min<real>(EPS_FLOOR, pL);
+  real th1 = 1.0;
   if (UH[0] < eps_rho) th1 = (rhoL - eps_rho) / (rhoL - UH[0]);
   Vec Us = UH;
   Us[0] = th1 * UH[0] + (1.0 - th1) * rhoL;
-  const double ps = pressure(Us, gamma);
-  double th2 = 1.0;
+  const real ps = pressure(Us, gamma);
+  real th2 = 1.0;
   if (ps < eps_p) th2 = (pL - eps_p) / (pL - ps);
   if (th1 < 1.0 || th2 < 1.0) ++cnt.n_point_limited;
-  auto make = [&](double t) {
+  auto make = [&](real t) {
     Vec W;
     for (int c = 0; c < NV; ++c) W[c] = t * Us[c] + (1.0 - t) * UL[c];
     return W;
@@ -284,22 +357,22 @@ Vec centre_value(const Access& acc, int i, int j, double gamma, Counters& cnt) {
   const Vec Vdl = acc.V(i, j), Vdr = acc.V(i + 1, j), Vul = acc.V(i, j + 1), Vur = acc.V(i + 1, j + 1);
   Vec Uc;
   for (int c = 0; c < NV; ++c) {
-    const double faces = (Xl[c] + Xr[c]) + (Yd[c] + Yu[c]);
-    const double corners = (Vdl[c] + Vdr[c]) + (Vul[c] + Vur[c]);
+    const real faces = (Xl[c] + Xr[c]) + (Yd[c] + Yu[c]);
+    const real corners = (Vdl[c] + Vdr[c]) + (Vul[c] + Vur[c]);
     Uc[c] = (36.0 * A[c] - 4.0 * faces - corners) / 16.0;
   }
-  const double rhoA = A[0], pA = pressure(A, gamma);
-  const double eps_rho = std::min(EPS_FLOOR, rhoA);
-  const double eps_p = std::min(EPS_FLOOR, pA);
-  double th1 = 1.0;
+  const real rhoA = A[0], pA = pressure(A, gamma);
+  const real eps_rho = std::min<real>(EPS_FLOOR, rhoA);
+  const real eps_p = std::min<real>(EPS_FLOOR, pA);
+  real th1 = 1.0;
   if (Uc[0] < eps_rho) th1 = (rhoA - eps_rho) / (rhoA - Uc[0]);
   Vec Ur;
   for (int c = 0; c < NV; ++c) Ur[c] = th1 * Uc[c] + (1.0 - th1) * A[c];
-  const double pr = pressure(Ur, gamma);
-  double th2 = 1.0;
+  const real pr = pressure(Ur, gamma);
+  real th2 = 1.0;
   if (pr < eps_p) th2 = (pA - eps_p) / (pA - pr);
   if (th1 < 1.0 || th2 < 1.0) ++cnt.n_centre_limited;
-  auto make = [&](double t) {
+  auto make = [&](real t) {
     Vec W;
     for (int c = 0; c < NV; ++c) W[c] = t * Ur[c] + (1.0 - t) * A[c];
     return W;
@@ -314,26 +387,26 @@ Vec centre_value(const Access& acc, int i, int j, double gamma, Counters& cnt) {
 // five stencil states w[0..4] sit at offsets -h, -h/2, 0, +h/2, +h.
 // alpha is the maximal spectral radius over the stencil.  Also returns the
 // central derivative 1/2 (D+ B_l + D- B_l) of the normal field component.
-void fvs_derivative(const Vec w[5], double gamma, int dir, double h, Vec& R, double& dB) {
+void fvs_derivative(const Vec w[5], double gamma, int dir, double h, Vec& R, real& dB) {
   Vec F[5];
-  double alpha = 0.0;
+  real alpha = 0.0;
   for (int m = 0; m < 5; ++m) {
     F[m] = flux(w[m], gamma, dir);
     alpha = std::max(alpha, spectral_radius(w[m], gamma, dir));
   }
   for (int c = 0; c < NV; ++c) {
-    double Fp[5], Fm[5];
+    real Fp[5], Fm[5];
     for (int m = 0; m < 5; ++m) {
       Fp[m] = 0.5 * (F[m][c] + alpha * w[m][c]);
       Fm[m] = 0.5 * (F[m][c] - alpha * w[m][c]);
     }
-    const double Dp = (Fp[0] - 4.0 * Fp[1] + 3.0 * Fp[2]) / h;
-    const double Dm = (-3.0 * Fm[2] + 4.0 * Fm[3] - Fm[4]) / h;
+    const real Dp = (Fp[0] - 4.0 * Fp[1] + 3.0 * Fp[2]) / h;
+    const real Dm = (-3.0 * Fm[2] + 4.0 * Fm[3] - Fm[4]) / h;
     R[c] = Dp + Dm;
   }
   const int b = 4 + dir;
-  const double Bp = (w[0][b] - 4.0 * w[1][b] + 3.0 * w[2][b]) / h;
-  const double Bm = (-3.0 * w[2][b] + 4.0 * w[3][b] - w[4][b]) / h;
+  const real Bp = (w[0][b] - 4.0 * w[1][b] + 3.0 * w[2][b]) / h;
+  const real Bm = (-3.0 * w[2][b] + 4.0 * w[3][b] - w[4][b]) / h;
   dB = 0.5 * (Bp + Bm);
 }
 
@@ -345,7 +418,7 @@ Vec point_llf(const Vec& U, const Vec& L, const Vec& R, const Vec& D, const Vec&
               const Grid& g) {
   const Vec FR = llf_flux(U, R, g.gamma, 0), FL = llf_flux(L, U, g.gamma, 0);
   const Vec FU = llf_flux(U, Up, g.gamma, 1), FD = llf_flux(D, U, g.gamma, 1);
-  const double divB = (R[4] - L[4]) / (2.0 * g.dx) + (Up[5] - D[5]) / (2.0 * g.dy);
+  const real divB = (R[4] - L[4]) / (2.0 * g.dx) + (Up[5] - D[5]) / (2.0 * g.dy);
   const Vec P = psi(U);
   Vec W;
   for (int c = 0; c < NV; ++c)
@@ -366,10 +439,10 @@ Vec vertex_high(const Access& acc, int k, int l, double dt, const Grid& g, Vec& 
   const Vec wx[5] = {acc.V(k - 1, l), acc.Y(k - 1, l), U, acc.Y(k, l), acc.V(k + 1, l)};
   const Vec wy[5] = {acc.V(k, l - 1), acc.X(k, l - 1), U, acc.X(k, l), acc.V(k, l + 1)};
   Vec R1, R2;
-  double d1, d2;
+  real d1, d2;
   fvs_derivative(wx, g.gamma, 0, g.dx, R1, d1);
   fvs_derivative(wy, g.gamma, 1, g.dy, R2, d2);
-  const double divB = d1 + d2;
+  const real divB = d1 + d2;
   const Vec P = psi(U);
   Vec H;
   for (int c = 0; c < NV; ++c) H[c] = U[c] + dt * (-R1[c] - R2[c] - divB * P[c]);
@@ -382,16 +455,16 @@ Vec xface_high(const Access& acc, const CentreField& C, int k, int j, double dt,
   U = acc.X(k, j);
   const Vec wx[5] = {acc.X(k - 1, j), C.at(k - 1, j), U, C.at(k, j), acc.X(k + 1, j)};
   Vec R1;
-  double d1;
+  real d1;
   fvs_derivative(wx, g.gamma, 0, g.dx, R1, d1);
   const Vec Vd = acc.V(k, j), Vu = acc.V(k, j + 1);
   const Vec Fd = flux(Vd, g.gamma, 1), Fu = flux(Vu, g.gamma, 1);
-  const double d2 = (Vu[5] - Vd[5]) / g.dy;
-  const double divB = d1 + d2;
+  const real d2 = (Vu[5] - Vd[5]) / g.dy;
+  const real divB = d1 + d2;
   const Vec P = psi(U);
   Vec H;
   for (int c = 0; c < NV; ++c) {
-    const double R2 = (Fu[c] - Fd[c]) / g.dy;
+    const real R2 = (Fu[c] - Fd[c]) / g.dy;
     H[c] = U[c] + dt * (-R1[c] - R2 - divB * P[c]);
   }
   return H;
@@ -403,16 +476,16 @@ Vec yface_high(const Access& acc, const CentreField& C, int i, int l, double dt,
   U = acc.Y(i, l);
   const Vec wy[5] = {acc.Y(i, l - 1), C.at(i, l - 1), U, C.at(i, l), acc.Y(i, l + 1)};
   Vec R2;
-  double d2;
+  real d2;
   fvs_derivative(wy, g.gamma, 1, g.dy, R2, d2);
   const Vec Vl = acc.V(i, l), Vr = acc.V(i + 1, l);
   const Vec Fl = flux(Vl, g.gamma, 0), Fr = flux(Vr, g.gamma, 0);
-  const double d1 = (Vr[4] - Vl[4]) / g.dx;
-  const double divB = d1 + d2;
+  const real d1 = (Vr[4] - Vl[4]) / g.dx;
+  const real divB = d1 + d2;
   const Vec P = psi(U);
   Vec H;
   for (int c = 0; c < NV; ++c) {
-    const double R1 = (Fr[c] - Fl[c]) / g.dx;
+    const real R1 = (Fr[c] - Fl[c]) / g.dx;
     H[c] = U[c] + dt * (-R1 - R2[c] - divB * P[c]);
   }
   return H;
@@ -452,7 +525,7 @@ Vec cell_source(const Access& acc, const CentreField& C, int i, int j, const Gri
   S9[1][2] = acc.Y(i, j + 1);
   S9[2][2] = acc.V(i + 1, j + 1);
   const double w[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
-  auto d3 = [](int at, double u0, double u1, double u2) {
+  auto d3 = [](int at, real u0, real u1, real u2) {
     if (at == 0) return -3.0 * u0 + 4.0 * u1 - u2;  // D^-
     if (at == 1) return u2 - u0;                    // D (central)
     return u0 - 4.0 * u1 + 3.0 * u2;                // D^+
@@ -460,9 +533,9 @@ Vec cell_source(const Access& acc, const CentreField& C, int i, int j, const Gri
   Vec S{};
   for (int a = 0; a < 3; ++a) {
     for (int b = 0; b < 3; ++b) {
-      const double dB1 = d3(a, S9[0][b][4], S9[1][b][4], S9[2][b][4]) / g.dx;
-      const double dB2 = d3(b, S9[a][0][5], S9[a][1][5], S9[a][2][5]) / g.dy;
-      const double divB = dB1 + dB2;
+      const real dB1 = d3(a, S9[0][b][4], S9[1][b][4], S9[2][b][4]) / g.dx;
+      const real dB2 = d3(b, S9[a][0][5], S9[a][1][5], S9[a][2][5]) / g.dy;
+      const real divB = dB1 + dB2;
       const Vec P = psi(S9[a][b]);
       for (int q = 0; q < NV; ++q) S[q] += w[a] * w[b] * divB * P[q];
     }
@@ -474,7 +547,7 @@ Vec cell_source(const Access& acc, const CentreField& C, int i, int j, const Gri
 // phi1 (Jameson on the total pressure, per direction), phi2 (modified
 // Ducros), phi3 (relative discrete divergence, as printed).
 struct Sensor {
-  double phi1x, phi1y, phi2, phi3;
+  real phi1x, phi1y, phi2, phi3;
 };
 Sensor cell_sensor(const Access& acc, int i, int j, const Grid& g) {
   const Vec c = acc.A(i, j);
@@ -482,36 +555,36 @@ Sensor cell_sensor(const Access& acc, int i, int j, const Grid& g) {
   auto pt = [&](const Vec& U) {
     return pressure(U, g.gamma) + (U[4] * U[4] + U[5] * U[5] + U[6] * U[6]) / 2.0;
   };
-  const double ptc = pt(c), ptl = pt(l), ptr = pt(r), ptd = pt(d), ptu = pt(u);
+  const real ptc = pt(c), ptl = pt(l), ptr = pt(r), ptd = pt(d), ptu = pt(u);
   Sensor s;
-  s.phi1x = std::fabs(ptr - 2.0 * ptc + ptl) / std::fabs(ptr + 2.0 * ptc + ptl);
-  s.phi1y = std::fabs(ptu - 2.0 * ptc + ptd) / std::fabs(ptu + 2.0 * ptc + ptd);
-  const double divv = (r[1] / r[0] - l[1] / l[0]) / (2.0 * g.dx) + (u[2] / u[0] - d[2] / d[0]) / (2.0 * g.dy);
-  const double curlv = (r[2] / r[0] - l[2] / l[0]) / (2.0 * g.dx) - (u[1] / u[0] - d[1] / d[0]) / (2.0 * g.dy);
-  s.phi2 = std::max(-divv / std::sqrt(divv * divv + curlv * curlv + 1e-40), 0.0);
-  s.phi3 = std::fabs(r[4] - l[4] + u[5] - d[5]) / (std::fabs(c[4] + c[5]) + 1e-40);
+  s.phi1x = fabs(ptr - 2.0 * ptc + ptl) / fabs(ptr + 2.0 * ptc + ptl);
+  s.phi1y = fabs(ptu - 2.0 * ptc + ptd) / fabs(ptu + 2.0 * ptc + ptd);
+  const real divv = (r[1] / r[0] - l[1] / l[0]) / (2.0 * g.dx) + (u[2] / u[0] - d[2] / d[0]) / (2.0 * g.dy);
+  const real curlv = (r[2] / r[0] - l[2] / l[0]) / (2.0 * g.dx) - (u[1] / u[0] - d[1] / d[0]) / (2.0 * g.dy);
+  s.phi2 = std::max<real>(-divv / sqrt(divv * divv + curlv * curlv + 1e-40), 0.0);
+  s.phi3 = fabs(r[4] - l[4] + u[5] - d[5]) / (fabs(c[4] + c[5]) + 1e-40);
   return s;
 }
 
-double sensor_theta(const Sensor& L, const Sensor& R, bool xdir, double kappa) {
-  const double p1 = xdir ? std::max(L.phi1x, R.phi1x) : std::max(L.phi1y, R.phi1y);
-  const double p2 = std::max(L.phi2, R.phi2);
-  const double p3 = std::max(L.phi3, R.phi3);
-  return std::exp(-kappa * (p1 * p2 + p3));
+real sensor_theta(const Sensor& L, const Sensor& R, bool xdir, double kappa) {
+  const real p1 = xdir ? std::max(L.phi1x, R.phi1x) : std::max(L.phi1y, R.phi1y);
+  const real p2 = std::max(L.phi2, R.phi2);
+  const real p3 = std::max(L.phi3, R.phi3);
+  return exp(-kappa * (p1 * p2 + p3));
 }
 
 // The pressure condition along the ray A1 + r D written as the cubic of
 // Section 3.2: q(r) = rho(r) [E(r) - |B(r)|^2/2 - eps_p/(gamma-1)] - |m(r)|^2/2,
 // which is rho(r) (p(r) - eps_p) / (gamma-1): same sign as p - eps_p while
 // rho > 0, but without the pole of p at rho = 0.  Returns q and dq/dr.
-void pressure_cubic(const Vec& A1, const Vec& D, double r, double gamma, double eps_p, double& q, double& dq) {
+void pressure_cubic(const Vec& A1, const Vec& D, real r, double gamma, real eps_p, real& q, real& dq) {
   Vec W;
   for (int c = 0; c < NV; ++c) W[c] = A1[c] + r * D[c];
-  const double b2 = W[4] * W[4] + W[5] * W[5] + W[6] * W[6];
-  const double m2 = W[1] * W[1] + W[2] * W[2] + W[3] * W[3];
-  const double e = W[7] - b2 / 2.0 - eps_p / (gamma - 1.0);
+  const real b2 = W[4] * W[4] + W[5] * W[5] + W[6] * W[6];
+  const real m2 = W[1] * W[1] + W[2] * W[2] + W[3] * W[3];
+  const real e = W[7] - b2 / 2.0 - eps_p / (gamma - 1.0);
   q = W[0] * e - m2 / 2.0;
-  const double de = D[7] - (W[4] * D[4] + W[5] * D[5] + W[6] * D[6]);
+  const real de = D[7] - (W[4] * D[4] + W[5] * D[5] + W[6] * D[6]);
   dq = D[0] * e + W[0] * de - (W[1] * D[1] + W[2] * D[2] + W[3] * D[3]);
 }
 
@@ -522,17 +595,17 @@ void pressure_cubic(const Vec& A1, const Vec& D, double r, double gamma, double 
 // started at r = 1 and kept inside the bracket [lo, hi] with q(lo) >= 0 > q(hi)
 // (a step leaving it is replaced by the midpoint); stop when the step is
 // <= 1e-13, at most 50 steps.
-double vertex_root(const Vec& A1, const Vec& D, double gamma, double eps_p, int& iters) {
-  double lo = 0.0, hi = 1.0, r = 1.0;
+real vertex_root(const Vec& A1, const Vec& D, double gamma, real eps_p, int& iters) {
+  real lo = 0.0, hi = 1.0, r = 1.0;
   iters = 0;
   for (int it = 0; it < 50; ++it) {
-    double q, dq;
+    real q, dq;
     pressure_cubic(A1, D, r, gamma, eps_p, q, dq);
     ++iters;
     if (q >= 0.0) lo = r; else hi = r;
-    double rn = r - q / dq;
+    real rn = r - q / dq;
     if (!(rn >= lo && rn <= hi)) rn = 0.5 * (lo + hi);
-    const double step = std::fabs(rn - r);
+    const real step = fabs(rn - r);
     r = rn;
     if (step <= 1e-13) break;
   }
@@ -542,17 +615,17 @@ double vertex_root(const Vec& A1, const Vec& D, double gamma, double eps_p, int&
 // Step (2) of the parametrized flux limiter, Section 3.2: the density box
 // Lambda^rho and the pressure shrink over the 15 non-trivial vertices.
 // H[0..3] = H_L, H_R, H_D, H_U.  Returns Lambda[0..3].
-void flux_limiter_box(const Vec& A1, const Vec H[4], double gamma, double eps_rho, double eps_p,
-                      double Lambda[4], Counters& cnt) {
-  double neg = 0.0;
+void flux_limiter_box(const Vec& A1, const Vec H[4], double gamma, real eps_rho, real eps_p,
+                      real Lambda[4], Counters& cnt) {
+  real neg = 0.0;
   for (int I = 0; I < 4; ++I)
     if (H[I][0] < 0.0) neg += H[I][0];
-  double Lr[4];
+  real Lr[4];
   for (int I = 0; I < 4; ++I) {
     Lr[I] = 1.0;
-    if (H[I][0] < 0.0) Lr[I] = std::min(1.0, (A1[0] - eps_rho) / (LAMBDA_REG - neg));
+    if (H[I][0] < 0.0) Lr[I] = std::min<real>(1.0, (A1[0] - eps_rho) / (LAMBDA_REG - neg));
   }
-  double rmin[4] = {1.0, 1.0, 1.0, 1.0};
+  real rmin[4] = {1.0, 1.0, 1.0, 1.0};
   bool any_root = false;
   for (int k = 1; k < 16; ++k) {
     Vec D{};
@@ -561,7 +634,7 @@ void flux_limiter_box(const Vec& A1, const Vec H[4], double gamma, double eps_rh
         for (int c = 0; c < NV; ++c) D[c] += Lr[I] * H[I][c];
     Vec W;
     for (int c = 0; c < NV; ++c) W[c] = A1[c] + D[c];
-    double r = 1.0;
+    real r = 1.0;
     if (pressure(W, gamma) < eps_p) {
       int it = 0;
       r = vertex_root(A1, D, gamma, eps_p, it);
@@ -575,7 +648,7 @@ void flux_limiter_box(const Vec& A1, const Vec H[4], double gamma, double eps_rh
   for (int I = 0; I < 4; ++I) Lambda[I] = Lr[I] * rmin[I];
   if (!any_root) return;  // the box corners are exactly the vertices checked above
   // Round-off fallback on the final box: all 15 corners must lie in G.
-  auto box_ok = [&](const double L[4]) {
+  auto box_ok = [&](const real L[4]) {
     for (int k = 1; k < 16; ++k) {
       Vec D{};
       for (int I = 0; I < 4; ++I)
@@ -590,8 +663,8 @@ void flux_limiter_box(const Vec& A1, const Vec H[4], double gamma, double eps_rh
   if (box_ok(Lambda)) return;
   ++cnt.n_fallback;
   for (int m = 0; m < 10; ++m) {
-    double L[4];
-    for (int I = 0; I < 4; ++I) L[I] = std::max(Lambda[I] - std::ldexp(SHRINK, m), 0.0);
+    real L[4];
+    for (int I = 0; I < 4; ++I) L[I] = std::max<real>(Lambda[I] - std::ldexp(SHRINK, m), 0.0);
     if (box_ok(L)) {
       for (int I = 0; I < 4; ++I) Lambda[I] = L[I];
       return;
@@ -605,8 +678,8 @@ struct CellWork {
   Vec A, S_s, S_llf;
   Vec FsL, FsR, FsD, FsU;      // sensor-blended high-order fluxes at the 4 interfaces
   Vec FlL, FlR, FlD, FlU;      // LLF fluxes at the 4 interfaces
-  double theta_src;
-  double Lambda[4];            // L, R, D, U
+  real theta_src;
+  real Lambda[4];            // L, R, D, U
 };
 
 // Steps (1) and (2) of the parametrized flux limiter, Section 3.2, for one
@@ -617,22 +690,22 @@ bool cell_limiter(CellWork& w, double dt, double dx, double dy, double gamma, Co
   const double ldx = dt / dx, ldy = dt / dy;
   Vec Allf, Asrc;
   for (int c = 0; c < NV; ++c) {
-    const double G = w.A[c] - ldx * (w.FlR[c] - w.FlL[c]) - ldy * (w.FlU[c] - w.FlD[c]);
+    const real G = w.A[c] - ldx * (w.FlR[c] - w.FlL[c]) - ldy * (w.FlU[c] - w.FlD[c]);
     Allf[c] = G - dt * w.S_llf[c];
     Asrc[c] = G - dt * w.S_s[c];
   }
   const bool llf_ok = in_G(Allf, gamma);
-  const double rhoL = Allf[0], pL = pressure(Allf, gamma);
-  const double eps_rho = std::min(EPS_FLOOR, rhoL);
-  const double eps_p = std::min(EPS_FLOOR, pL);
+  const real rhoL = Allf[0], pL = pressure(Allf, gamma);
+  const real eps_rho = std::min<real>(EPS_FLOOR, rhoL);
+  const real eps_p = std::min<real>(EPS_FLOOR, pL);
   // Step (1): limit the source term.
-  double th = 1.0;
-  const double psrc = pressure(Asrc, gamma);
+  real th = 1.0;
+  const real psrc = pressure(Asrc, gamma);
   if (psrc < eps_p) {
     th = (pL - eps_p) / (pL - psrc);
     ++cnt.n_source_limited;
   }
-  auto make = [&](double t) {
+  auto make = [&](real t) {
     Vec W;
     for (int c = 0; c < NV; ++c) W[c] = t * Asrc[c] + (1.0 - t) * Allf[c];
     return W;
@@ -661,7 +734,7 @@ struct Stage {
   Counters cnt;
 
   // out = a * Un + b * FE(Uk), for all four DoF sets.
-  void run(StateView un, double* const out[4], double a, double b, int nthreads);
+  void run(StateView un, real* const out[4], double a, double b, int nthreads);
 };
 
 inline size_t cidx(const Grid& g, int c, int i, int j) { return ((size_t)c * g.ny + j) * g.nx + i; }
@@ -669,7 +742,7 @@ inline size_t xidx(const Grid& g, int c, int k, int j) { return ((size_t)c * g.n
 inline size_t yidx(const Grid& g, int c, int i, int l) { return ((size_t)c * g.nyp + l) * g.nx + i; }
 inline size_t vidx(const Grid& g, int c, int k, int l) { return ((size_t)c * g.nyp + l) * g.nxp + k; }
 
-void Stage::run(StateView un, double* const out[4], double a, double b, int nthreads) {
+void Stage::run(StateView un, real* const out[4], double a, double b, int nthreads) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -677,7 +750,7 @@ void Stage::run(StateView un, double* const out[4], double a, double b, int nthr
 #endif
   const int nx = g.nx, ny = g.ny, nxp = g.nxp, nyp = g.nyp;
   const bool first = (a == 0.0 && b == 1.0);
-  auto combine = [&](double un_v, double fe) { return first ? fe : a * un_v + b * fe; };
+  auto combine = [&](real un_v, real fe) { return first ? fe : a * un_v + b * fe; };
 
   // Centre values (limited) on cells [-2, nx+2) x [-2, ny+2).
   CentreField C;
@@ -777,16 +850,16 @@ void Stage::run(StateView un, double* const out[4], double a, double b, int nthr
   // and y-interfaces l in [-1, ny+2), columns i in [-1, nx+1).
   const int xw = nx + 3, yw = nx + 2;
   std::vector<Vec> FsX((size_t)xw * (ny + 2)), FlX((size_t)xw * (ny + 2));
-  std::vector<double> tsX((size_t)xw * (ny + 2));
+  std::vector<real> tsX((size_t)xw * (ny + 2));
   std::vector<Vec> FsY((size_t)yw * (ny + 3)), FlY((size_t)yw * (ny + 3));
-  std::vector<double> tsY((size_t)yw * (ny + 3));
+  std::vector<real> tsY((size_t)yw * (ny + 3));
 #pragma omp parallel for schedule(static)
   for (int j = -1; j < ny + 1; ++j)
     for (int k = -1; k < nx + 2; ++k) {
       const size_t id = (size_t)(j + 1) * xw + (k + 1);
       const Vec Fh = simpson_x(acc, k, j, g.gamma);
       const Vec Fl = llf_flux(acc.A(k - 1, j), acc.A(k, j), g.gamma, 0);
-      const double ts = sensor_theta(S_at(k - 1, j), S_at(k, j), true, g.kappa);
+      const real ts = sensor_theta(S_at(k - 1, j), S_at(k, j), true, g.kappa);
       Vec Fs;
       for (int c = 0; c < NV; ++c) Fs[c] = ts * Fh[c] + (1.0 - ts) * Fl[c];
       FsX[id] = Fs;
@@ -799,7 +872,7 @@ void Stage::run(StateView un, double* const out[4], double a, double b, int nthr
       const size_t id = (size_t)(l + 1) * yw + (i + 1);
       const Vec Fh = simpson_y(acc, i, l, g.gamma);
       const Vec Fl = llf_flux(acc.A(i, l - 1), acc.A(i, l), g.gamma, 1);
-      const double ts = sensor_theta(S_at(i, l - 1), S_at(i, l), false, g.kappa);
+      const real ts = sensor_theta(S_at(i, l - 1), S_at(i, l), false, g.kappa);
       Vec Fs;
       for (int c = 0; c < NV; ++c) Fs[c] = ts * Fh[c] + (1.0 - ts) * Fl[c];
       FsY[id] = Fs;
@@ -831,9 +904,9 @@ void Stage::run(StateView un, double* const out[4], double a, double b, int nthr
       // cell averages), and the sensor blend with the smallest interface theta.
       const Vec S = cell_source(acc, C, i, j, g);
       const Vec Al = acc.A(i - 1, j), Ar = acc.A(i + 1, j), Ad = acc.A(i, j - 1), Au = acc.A(i, j + 1);
-      const double divBbar = (Ar[4] - Al[4]) / (2.0 * g.dx) + (Au[5] - Ad[5]) / (2.0 * g.dy);
+      const real divBbar = (Ar[4] - Al[4]) / (2.0 * g.dx) + (Au[5] - Ad[5]) / (2.0 * g.dy);
       const Vec P = psi(w.A);
-      const double ts_ij = std::min(std::min(tsX[xid(i, j)], tsX[xid(i + 1, j)]),
+      const real ts_ij = std::min(std::min(tsX[xid(i, j)], tsX[xid(i + 1, j)]),
                                     std::min(tsY[yid(i, j)], tsY[yid(i, j + 1)]));
       for (int c = 0; c < NV; ++c) {
         w.S_llf[c] = divBbar * P[c];
@@ -858,23 +931,23 @@ void Stage::run(StateView un, double* const out[4], double a, double b, int nthr
     Counters cc;
     for (int i = 0; i < nx; ++i) {
       const CellWork& w = cwat(i, j);
-      const double thL = std::min(cwat(i - 1, j).Lambda[1], w.Lambda[0]);
-      const double thR = std::min(w.Lambda[1], cwat(i + 1, j).Lambda[0]);
-      const double thD = std::min(cwat(i, j - 1).Lambda[3], w.Lambda[2]);
-      const double thU = std::min(w.Lambda[3], cwat(i, j + 1).Lambda[2]);
+      const real thL = std::min(cwat(i - 1, j).Lambda[1], w.Lambda[0]);
+      const real thR = std::min(w.Lambda[1], cwat(i + 1, j).Lambda[0]);
+      const real thD = std::min(cwat(i, j - 1).Lambda[3], w.Lambda[2]);
+      const real thU = std::min(w.Lambda[3], cwat(i, j + 1).Lambda[2]);
       // count each interface once: the left and bottom ones of the cell
       if (thL < 1.0) ++cc.n_theta_active;
       if (thD < 1.0) ++cc.n_theta_active;
       if ((g.bcx == 1 && i == nx - 1) && thR < 1.0) ++cc.n_theta_active;
       if ((g.bcy == 1 && j == ny - 1) && thU < 1.0) ++cc.n_theta_active;
-      cc.min_theta = std::min(cc.min_theta, std::min(std::min(thL, thR), std::min(thD, thU)));
+      cc.min_theta = std::min(cc.min_theta, val(std::min(std::min(thL, thR), std::min(thD, thU))));
       Vec Anew;
       for (int c = 0; c < NV; ++c) {
-        const double FL = thL * w.FsL[c] + (1.0 - thL) * w.FlL[c];
-        const double FR = thR * w.FsR[c] + (1.0 - thR) * w.FlR[c];
-        const double FD = thD * w.FsD[c] + (1.0 - thD) * w.FlD[c];
-        const double FU = thU * w.FsU[c] + (1.0 - thU) * w.FlU[c];
-        const double S = w.theta_src * w.S_s[c] + (1.0 - w.theta_src) * w.S_llf[c];
+        const real FL = thL * w.FsL[c] + (1.0 - thL) * w.FlL[c];
+        const real FR = thR * w.FsR[c] + (1.0 - thR) * w.FlR[c];
+        const real FD = thD * w.FsD[c] + (1.0 - thD) * w.FlD[c];
+        const real FU = thU * w.FsU[c] + (1.0 - thU) * w.FlU[c];
+        const real S = w.theta_src * w.S_s[c] + (1.0 - w.theta_src) * w.S_llf[c];
         Anew[c] = w.A[c] - ldx * (FR - FL) - ldy * (FU - FD) - dt * S;
       }
       if (!in_G(Anew, g.gamma)) ++cc.n_not_admissible;
@@ -893,16 +966,16 @@ void Stage::run(StateView un, double* const out[4], double a, double b, int nthr
 }
 
 // Time step: dt = min(CFL / max over all DoFs of (rho_1/dx + rho_2/dy), t_remaining).
-double compute_dt(const Grid& g, StateView s, double cfl, double t_remaining) {
+real compute_dt(const Grid& g, StateView s, double cfl, double t_remaining) {
   double mx = 0.0;
-  auto visit = [&](const double* base, int w, int h) {
+  auto visit = [&](const real* base, int w, int h) {
     double m = 0.0;
 #pragma omp parallel for reduction(max : m) schedule(static)
     for (int j = 0; j < h; ++j)
       for (int i = 0; i < w; ++i) {
         Vec U;
         for (int c = 0; c < NV; ++c) U[c] = base[((size_t)c * h + j) * w + i];
-        const double q = spectral_radius(U, g.gamma, 0) / g.dx + spectral_radius(U, g.gamma, 1) / g.dy;
+        const double q = val(spectral_radius(U, g.gamma, 0)) / g.dx + val(spectral_radius(U, g.gamma, 1)) / g.dy;
         m = std::max(m, q);
       }
     mx = std::max(mx, m);
@@ -964,6 +1037,89 @@ static void export_counters(const Counters& c, orc_counters* o) {
   o->min_theta = std::min(o->min_theta, c.min_theta);
 }
 
+#ifdef ORC_TANGENT
+// ---- tangent build: values with ORC_TANGENT directional derivatives.
+// A state with derivatives is 4 value arrays (cell, xface, yface, vert) and
+// 4 derivative arrays laid out [ORC_TANGENT][size of the set].
+static const double RK_A[3] = {0.0, 0.75, 1.0 / 3.0};
+static const double RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
+
+static void set_sizes(const Grid& g, size_t n[4]) {
+  n[0] = (size_t)NV * g.nx * g.ny;
+  n[1] = (size_t)NV * g.nxp * g.ny;
+  n[2] = (size_t)NV * g.nx * g.nyp;
+  n[3] = (size_t)NV * g.nxp * g.nyp;
+}
+static void pack(const double* v, const double* d, size_t n, std::vector<real>& out) {
+  out.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    out[i] = real(v[i]);
+    for (int q = 0; q < tangent::ND; ++q) out[i].d[q] = d[(size_t)q * n + i];
+  }
+}
+static void unpack(const std::vector<real>& in, double* v, double* d) {
+  const size_t n = in.size();
+  for (size_t i = 0; i < n; ++i) {
+    v[i] = in[i].v;
+    for (int q = 0; q < tangent::ND; ++q) d[(size_t)q * n + i] = in[i].d[q];
+  }
+}
+
+int orc_t_nd(void) { return tangent::ND; }
+
+// out = a_k Un + b_k FE(Uk) and its directional derivatives; dt is fixed.
+int orc_t_stage(const orc_params* p, int k, const double* const* un, const double* const* dun,
+                const double* const* uk, const double* const* duk, double* const* out, double* const* dout,
+                double dt) {
+  if (!p || k < 0 || k > 2 || p->nx < 4 || p->ny < 4) return -1;
+  const Grid g = make_grid(p);
+  size_t n[4];
+  set_sizes(g, n);
+  std::vector<real> vn[4], vk[4], vo[4];
+  real* po[4];
+  for (int q = 0; q < 4; ++q) {
+    pack(un[q], dun[q], n[q], vn[q]);
+    pack(uk[q], duk[q], n[q], vk[q]);
+    vo[q].resize(n[q]);
+    po[q] = vo[q].data();
+  }
+  Stage st{g, Access{g, StateView{vk[0].data(), vk[1].data(), vk[2].data(), vk[3].data()}}, dt, Counters()};
+  st.run(StateView{vn[0].data(), vn[1].data(), vn[2].data(), vn[3].data()}, po, RK_A[k], RK_B[k], p->nthreads);
+  for (int q = 0; q < 4; ++q) unpack(vo[q], out[q], dout[q]);
+  return 0;
+}
+
+// nsteps SSP-RK3 steps in place with the given time steps dts[nsteps] (the
+// step sizes are data, not differentiated).
+int orc_t_run(const orc_params* p, int nsteps, const double* dts, double* const* u, double* const* du) {
+  if (!p || nsteps < 0 || p->nx < 4 || p->ny < 4) return -1;
+  const Grid g = make_grid(p);
+  size_t n[4];
+  set_sizes(g, n);
+  std::vector<real> s0[4], s1[4], s2[4];
+  real *p0[4], *p1[4], *p2[4];
+  for (int q = 0; q < 4; ++q) {
+    pack(u[q], du[q], n[q], s0[q]);
+    s1[q].resize(n[q]);
+    s2[q].resize(n[q]);
+    p0[q] = s0[q].data();
+    p1[q] = s1[q].data();
+    p2[q] = s2[q].data();
+  }
+  const StateView v0{p0[0], p0[1], p0[2], p0[3]}, v1{p1[0], p1[1], p1[2], p1[3]}, v2{p2[0], p2[1], p2[2], p2[3]};
+  for (int s = 0; s < nsteps; ++s) {
+    Stage a{g, Access{g, v0}, dts[s], Counters()};
+    a.run(v0, p1, RK_A[0], RK_B[0], p->nthreads);
+    Stage b{g, Access{g, v1}, dts[s], Counters()};
+    b.run(v0, p2, RK_A[1], RK_B[1], p->nthreads);
+    Stage c{g, Access{g, v2}, dts[s], Counters()};
+    c.run(v0, p1, RK_A[2], RK_B[2], p->nthreads);
+    for (int q = 0; q < 4; ++q) std::copy(s1[q].begin(), s1[q].end(), s0[q].begin());
+  }
+  for (int q = 0; q < 4; ++q) unpack(s0[q], u[q], du[q]);
+  return 0;
+}
+#else
 // out = a_k Un + b_k FE(Uk) with (a,b) = (0,1), (3/4,1/4), (1/3,2/3).
 // Each state is given as 4 pointers: cell, xface, yface, vert.
 int orc_stage(const orc_params* p, int k, const double* const* un, const double* const* uk,
@@ -1219,5 +1375,7 @@ void orc_divb(const orc_params* p, const double* const* u, double* out2) {
   out2[0] = div1;
   out2[1] = div2;
 }
+
+#endif  // ORC_TANGENT
 
 }  // extern "C"

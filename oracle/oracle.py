@@ -22,19 +22,28 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "af_oracle.cpp")
 LIB = os.environ.get("AF_ORACLE_LIB") or os.path.join(HERE, "_build", "liboracle.so")
+# The same source built on forward-mode dual numbers (-DORC_TANGENT=TANGENT_ND):
+# exact directional derivatives of the discrete stage, the adjoint's reference.
+TANGENT_ND = 8
+TLIB = os.path.join(HERE, "_build", "liboracle_tangent.so")
 
 # -O2 without -march=native: the library is built here and may run on another host.
 CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 
+def _compile(out: str, extra: list) -> None:
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++", *CXXFLAGS, *extra, SRC, "-o", tmp])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle into ``oracle/_build/liboracle.so``."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["g++", *CXXFLAGS, SRC, "-o", tmp])
-    os.replace(tmp, LIB)
+    """Compile the oracle into ``oracle/_build/liboracle.so`` and its tangent
+    build into ``oracle/_build/liboracle_tangent.so``."""
+    for out, extra in ((LIB, []), (TLIB, ["-DORC_TANGENT=%d" % TANGENT_ND])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            _compile(out, extra)
     return LIB
 
 
@@ -311,3 +320,75 @@ def cell_limiter(A, Fs, Fl, S_s, S_llf, dt, dx, dy, gamma):
     lib().orc_cell_limiter(_ptr(_vec(A)), _ptr(F), _ptr(S), dt, dx, dy, gamma, ctypes.byref(th), _ptr(lam),
                            _ptr(a1), ctypes.byref(nf))
     return th.value, lam, a1, nf.value
+
+
+# ---- tangent oracle: directional derivatives of the discrete map
+_tlib = None
+
+
+def tlib():
+    global _tlib
+    if _tlib is None:
+        if not os.path.exists(TLIB):
+            build(force=False)
+        L = ctypes.CDLL(TLIB)
+        L.orc_t_nd.restype = ctypes.c_int
+        L.orc_t_stage.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _DD, _DD, _DD, _DD, _DD, _DD,
+                                  ctypes.c_double]
+        L.orc_t_stage.restype = ctypes.c_int
+        L.orc_t_run.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _D, _DD, _DD]
+        L.orc_t_run.restype = ctypes.c_int
+        assert L.orc_t_nd() == TANGENT_ND
+        _tlib = L
+    return _tlib
+
+
+def _stack_dirs(dirs, lo, state):
+    """Directions lo .. lo+TANGENT_ND-1 (zeros past the end) as 4 arrays
+    [TANGENT_ND, *shape of the set]."""
+    out = []
+    for q, a in enumerate(state):
+        t = np.zeros((TANGENT_ND,) + a.shape)
+        for d in range(TANGENT_ND):
+            if lo + d < len(dirs):
+                t[d] = dirs[lo + d][q]
+        out.append(np.ascontiguousarray(t))
+    return out
+
+
+def tangent_stage(prob, k: int, un, dun, uk, duk, dt: float, nthreads: int = 0):
+    """a_k U^n + b_k FE(U^(k), dt) and its derivatives along the directions
+    (dun[d], duk[d]) (each a state-shaped tuple).  Returns (out, [dout_d])."""
+    assert len(dun) == len(duk)
+    out = empty_like_state(un)
+    vn, vk = copy_state(un), copy_state(uk)  # kept alive across the call
+    douts = []
+    for lo in range(0, max(len(dun), 1), TANGENT_ND):
+        tn, tk = _stack_dirs(dun, lo, un), _stack_dirs(duk, lo, uk)
+        to = [np.empty_like(a) for a in tn]
+        rc = tlib().orc_t_stage(ctypes.byref(_params(prob, nthreads)), k, _ptrs(vn), _ptrs(tn),
+                                _ptrs(vk), _ptrs(tk), _ptrs(out), _ptrs(to), dt)
+        if rc != 0:
+            raise ValueError("tangent stage rejected its arguments (rc=%d)" % rc)
+        for d in range(TANGENT_ND):
+            if lo + d < len(dun):
+                douts.append(tuple(np.ascontiguousarray(t[d]) for t in to))
+    return out, douts
+
+
+def tangent_run(prob, u, du, dts, nthreads: int = 0):
+    """len(dts) SSP-RK3 steps with the given step sizes, with the derivatives
+    along the directions du[d].  Returns (state, [d state_d])."""
+    dts = np.ascontiguousarray(dts, dtype=np.float64)
+    douts = []
+    v = None
+    for lo in range(0, max(len(du), 1), TANGENT_ND):
+        v = copy_state(u)
+        t = _stack_dirs(du, lo, u)
+        rc = tlib().orc_t_run(ctypes.byref(_params(prob, nthreads)), len(dts), _ptr(dts), _ptrs(v), _ptrs(t))
+        if rc != 0:
+            raise ValueError("tangent run rejected its arguments (rc=%d)" % rc)
+        for d in range(TANGENT_ND):
+            if lo + d < len(du):
+                douts.append(tuple(np.ascontiguousarray(x[d]) for x in t))
+    return v, douts

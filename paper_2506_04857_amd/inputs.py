@@ -308,8 +308,85 @@ def random_shock(n: int = 16, ny: int | None = None, seed: int = BASE_SEED, bc: 
     return Problem("random_shock", n, ny, 0.0, 1.0, 0.0, ny / n, 1.4, 0.2, 1.0, bc, bc, 1.0, prim)
 
 
+def stirred(base: Problem, eps: float = 1e-2) -> Problem:
+    """base with a small smooth velocity field added (eps sin / cos waves in
+    v1 and v2): the shock sensor's phi2 = -div v / |(div v, curl v)| is then
+    differentiable everywhere, also in regions where base has a constant
+    velocity (there div v and curl v are rounding noise and phi2 is 0/0)."""
+    def prim(x, y, t):
+        w = np.array(base.prim(x, y, t) * np.ones_like(np.asarray(x, dtype=np.float64)), dtype=np.float64)
+        w[1] = w[1] + eps * np.sin(2 * math.pi * (x + 2 * y) + 0.3)
+        w[2] = w[2] + eps * np.cos(2 * math.pi * (2 * x - y) + 1.1)
+        return w
+
+    return replace(base, name=base.name + "_stirred", prim=prim)
+
+
+ADJOINT_STEPS = 400
+
+
+def alfven_perturbed(n: int = 256, seed: int = BASE_SEED + 999, amp: float = 1e-3) -> Problem:
+    """The Alfven wave of ``alfven`` plus a seeded smooth perturbation of
+    amplitude ``amp`` in rho and B1 (the adjoint workload, 256^2 by default).
+
+    drho = amp * s / max|s| with s = sum_q a_q sin(2 pi (m_q x + n_q y)/L + psi_q),
+    dB1  = amp * t / max|t| with t = sum_q b_q sin(2 pi n'_q y / L + chi_q),
+    q = 1..3, L = sqrt(2) (the side of the domain), m, n, n' drawn from {1,2,3},
+    a, b ~ N(0,1), phases ~ U[0, 2 pi), all from default_rng(seed) in that
+    order; the maxima are taken on a 512 x 512 lattice of the periodic domain.
+    dB1 depends on y only, so div B stays zero; p and the other primitives
+    are those of the wave, and the conservative variables are recomputed."""
+    base = alfven(n)
+    L = base.x1 - base.x0
+    rng = np.random.default_rng(seed)
+    m = rng.integers(1, 4, size=3)
+    nn = rng.integers(1, 4, size=3)
+    a = rng.standard_normal(3)
+    psi = rng.uniform(0.0, 2 * math.pi, size=3)
+    nb = rng.integers(1, 4, size=3)
+    b = rng.standard_normal(3)
+    chi = rng.uniform(0.0, 2 * math.pi, size=3)
+
+    def s_rho(x, y):
+        return sum(a[q] * np.sin(2 * math.pi * (m[q] * x + nn[q] * y) / L + psi[q]) for q in range(3))
+
+    def s_b1(y):
+        return sum(b[q] * np.sin(2 * math.pi * nb[q] * y / L + chi[q]) for q in range(3))
+
+    lat = np.arange(512) * (L / 512)
+    X, Y = np.meshgrid(lat, lat)
+    norm_rho = amp / np.max(np.abs(s_rho(X, Y)))
+    norm_b1 = amp / np.max(np.abs(s_b1(lat)))
+
+    def prim(x, y, t):
+        w = base.prim(x, y, t)
+        w = np.array(w * np.ones_like(np.asarray(x, dtype=np.float64)), dtype=np.float64)
+        w[0] = w[0] + norm_rho * s_rho(x, y)
+        w[4] = w[4] + norm_b1 * s_b1(y)
+        return w
+
+    return replace(base, name="alfven_perturbed", prim=prim)
+
+
+def adjoint_objective_target(prob: Problem) -> float:
+    """rho_target of J = 1/2 sum_cells (rho(T) - rho_target)^2: the density of
+    the unperturbed wave, which is 1 everywhere at every time."""
+    return 1.0
+
+
+def adjoint_directions(prob: Problem, count: int = 20, seed: int = BASE_SEED + 1000) -> list:
+    """Unit-Gaussian directions over all 32 planes of the initial state for
+    the finite-difference check: direction k from default_rng(seed + k)."""
+    out = []
+    for k in range(count):
+        rng = np.random.default_rng(seed + k)
+        out.append(tuple(rng.standard_normal(s) for s in prob.shapes()))
+    return out
+
+
 CONFIGS = {
     "alfven_32": lambda: alfven(32),
     "orszag_tang_512": lambda: orszag_tang(512),
     "blast_lowbeta_1024": lambda: blast_lowbeta(1024),
+    "alfven_perturbed_256": lambda: alfven_perturbed(256),
 }
