@@ -115,6 +115,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.af_mhd_batch_last_error.restype = ctypes.c_char_p
     L.af_mhd_destroy.argtypes = [vp]
     L.af_mhd_destroy.restype = None
+    L.af_mhd_adj_tape_bytes.argtypes = [P]
+    L.af_mhd_adj_tape_bytes.restype = ctypes.c_size_t
+    L.af_mhd_adj_workspace_bytes.argtypes = [P]
+    L.af_mhd_adj_workspace_bytes.restype = ctypes.c_size_t
+    L.af_mhd_adj_init.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.af_mhd_adj_init.restype = ctypes.c_int
+    L.af_mhd_adj_record.argtypes = [vp, ctypes.c_int, S, S, S, vp, vp, ctypes.c_size_t]
+    L.af_mhd_adj_record.restype = ctypes.c_int
+    L.af_mhd_adj_stage.argtypes = [vp, ctypes.c_int, S, vp, ctypes.c_size_t, vp, S, S, S]
+    L.af_mhd_adj_stage.restype = ctypes.c_int
+    L.af_mhd_adj_destroy.argtypes = [vp]
+    L.af_mhd_adj_destroy.restype = None
+    L.af_mhd_adj_last_error.argtypes = [vp]
+    L.af_mhd_adj_last_error.restype = ctypes.c_char_p
     L.af_mhd_last_error.argtypes = [vp]
     L.af_mhd_last_error.restype = ctypes.c_char_p
     return L
@@ -315,6 +329,188 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Adjoint:
+    """Owns one af_mhd_adj (the recorded stage and its reverse sweep) and its
+    workspace.  FP64 only."""
+
+    def __init__(self, prob, device=None, stream=None):
+        import torch
+
+        self.prob = prob
+        self.params = make_params(prob, 0)
+        nbytes = int(_lib.af_mhd_adj_workspace_bytes(ctypes.byref(self.params)))
+        if nbytes == 0:
+            raise AfMhdError(AF_EINVAL, "invalid parameters")
+        self.tape_bytes = int(_lib.af_mhd_adj_tape_bytes(ctypes.byref(self.params)))
+        self.device = torch.device(device if device is not None else "cuda")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ws = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = _lib.af_mhd_adj_init(ctypes.byref(self.params), ctypes.c_void_p(ws), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != AF_OK:
+            raise AfMhdError(rc, "af_mhd_adj_init failed: " + _lib.af_mhd_adj_last_error(None).decode())
+        self._h = h
+
+    def _check(self, rc: int):
+        if rc != AF_OK:
+            raise AfMhdError(rc, _lib.af_mhd_adj_last_error(self._h).decode())
+
+    def new_tape(self):
+        """A device buffer for one stage's tape (256-byte aligned view)."""
+        import torch
+
+        buf = torch.empty(self.tape_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        return buf[off:off + self.tape_bytes]
+
+    def record(self, k: int, un, uk, out, dt_dev, tape):
+        """out = a_k un + b_k FE(uk, dt) and the stage's tape."""
+        self._check(_lib.af_mhd_adj_record(self._h, k, ctypes.byref(_state(un)), ctypes.byref(_state(uk)),
+                                           ctypes.byref(_state(out)), ctypes.c_void_p(dt_dev.data_ptr()),
+                                           ctypes.c_void_p(tape.data_ptr()), tape.numel()))
+        return out
+
+    def stage(self, k: int, uk, tape, dt_dev, lam_out, lam_n, lam_k):
+        """lam_n += a_k lam_out; lam_k += b_k J^T lam_out (k = 0: lam_n unused)."""
+        ln = ctypes.byref(_state(lam_n)) if lam_n is not None else None
+        self._check(_lib.af_mhd_adj_stage(self._h, k, ctypes.byref(_state(uk)), ctypes.c_void_p(tape.data_ptr()),
+                                          tape.numel(), ctypes.c_void_p(dt_dev.data_ptr()),
+                                          ctypes.byref(_state(lam_out)), ln, ctypes.byref(_state(lam_k))))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.af_mhd_adj_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CheckpointedRun:
+    """n SSP-RK3 steps of one grid with the gradient of their end state by
+    the discrete adjoint and sqrt(n) checkpointing.
+
+    forward(): the fast stage kernels advance the state, keep the state every
+    `every` steps (default ceil(sqrt(n))) and the dt of every step in device
+    memory.  backward(lam): for each segment, last first, the recording
+    stage recomputes the segment from its checkpoint (keeping its stage
+    inputs and tapes, 3 per step), then the reverse sweep runs its steps
+    backwards.  The dt sequence is data (frozen), not differentiated."""
+
+    def __init__(self, prob, device=None, every: int | None = None):
+        import torch
+
+        self.prob = prob
+        self.device = torch.device(device if device is not None else "cuda")
+        self.ctx = Context(prob, device=self.device)
+        self.adj = Adjoint(prob, device=self.device, stream=self.ctx.stream)
+        self.every = every
+        self.dts = None
+        self.checkpoints = []
+
+    def _zeros(self):
+        import torch
+
+        return tuple(torch.zeros(s, dtype=torch.float64, device=self.device) for s in self.prob.shapes())
+
+    def forward(self, u0, nsteps: int, dts=None, t_final: float = float("inf")):
+        """Returns the end state (new tensors).  dts: a device tensor of fixed
+        step sizes to use instead of the CFL rule."""
+        import math
+
+        import torch
+
+        every = self.every or max(1, math.isqrt(max(nsteps - 1, 0)) + 1)
+        self.every = every
+        u = tuple(t.clone() for t in u0)
+        self.nsteps = nsteps
+        self.checkpoints = []
+        if dts is not None:
+            self.dts = dts.to(self.device, torch.float64).contiguous()
+            assert self.dts.numel() >= nsteps
+        else:
+            self.dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=self.device)
+        s1, s2 = self._zeros(), self._zeros()
+        t = 0.0
+        for s in range(nsteps):
+            if s % every == 0:
+                self.checkpoints.append(tuple(x.clone() for x in u))
+            if dts is None:
+                self.ctx.af_mhd_step(u, t_final - t if math.isfinite(t_final) else float("inf"))
+                self.dts[s:s + 1].copy_(self.ctx.dt_dev)
+            else:
+                d = self.dts[s:s + 1]
+                self.ctx.af_mhd_stage(0, u, u, s1, d)
+                self.ctx.af_mhd_stage(1, u, s1, s2, d)
+                self.ctx.af_mhd_stage(2, u, s2, u, d)
+        return u
+
+    def backward(self, lam_T):
+        """Adjoint of the initial state given lam_T, the adjoint of the end
+        state (a tuple of 4 device tensors, not modified)."""
+        lam = tuple(x.clone() for x in lam_T)
+        every = self.every
+        for c in reversed(range(len(self.checkpoints))):
+            first = c * every
+            last = min(first + every, self.nsteps)
+            hist = []
+            u = self.checkpoints[c]
+            for s in range(first, last):
+                d = self.dts[s:s + 1]
+                u1, u2, u3 = self._zeros(), self._zeros(), self._zeros()
+                t0, t1, t2 = self.adj.new_tape(), self.adj.new_tape(), self.adj.new_tape()
+                self.adj.record(0, u, u, u1, d, t0)
+                self.adj.record(1, u, u1, u2, d, t1)
+                self.adj.record(2, u, u2, u3, d, t2)
+                hist.append((u, u1, u2, t0, t1, t2, d))
+                u = u3
+            for un, u1, u2, t0, t1, t2, d in reversed(hist):
+                ln, l2, l1 = self._zeros(), self._zeros(), self._zeros()
+                self.adj.stage(2, u2, t2, d, lam, ln, l2)
+                self.adj.stage(1, u1, t1, d, l2, ln, l1)
+                self.adj.stage(0, un, t0, d, l1, None, ln)
+                lam = ln
+            del hist
+        return lam
+
+    def close(self):
+        self.adj.close()
+        self.ctx.close()
+
+
+def evolve(prob, u0, nsteps: int, every: int | None = None, dts=None):
+    """End state of nsteps SSP-RK3 steps from u0 (4 float64 device tensors)
+    as a differentiable torch function: backward runs the discrete adjoint
+    with sqrt(n) checkpointing (decisions of the limiters and the sensor
+    frozen as the recomputation takes them, dt sequence fixed)."""
+    import torch
+
+    class _Evolve(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, *u):
+            run = CheckpointedRun(prob, device=u[0].device, every=every)
+            out = run.forward(tuple(x.detach() for x in u), nsteps, dts=dts)
+            ctx.run = run
+            return out
+
+        @staticmethod
+        def backward(ctx, *g):
+            run = ctx.run
+            lam_T = tuple(gi.contiguous() if gi is not None else torch.zeros(s, dtype=torch.float64,
+                                                                              device=run.device)
+                          for gi, s in zip(g, prob.shapes()))
+            lam0 = run.backward(lam_T)
+            run.close()
+            return lam0
+
+    return _Evolve.apply(*u0)
 
 
 def to_device(state, device="cuda"):

@@ -8,6 +8,13 @@
 // adjoint states and into the intermediate adjoint buffers of the
 // workspace, so its sums are order-dependent at the rounding level (not
 // bitwise reproducible run to run).
+// No contraction of a*b+c into fused multiply-adds in this translation unit
+// (it must precede the includes to cover the entity functions): the
+// recording forward and the reverse sweep then round like the FP64 oracle,
+// so exact cancellations on symmetric data stay exact and the branches taken
+// at them (|0|, max ties) are the oracle's.
+#pragma clang fp contract(off)
+
 #include <hip/hip_runtime.h>
 
 #include <new>
