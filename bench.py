@@ -6,6 +6,10 @@ timed region).
 python bench.py [--steps K] [--warmup W] [--workload orszag_tang_512|blast_lowbeta_1024|alfven_32]
 Prints one JSON line.
 
+Also measured (objects of the same line): the batched ensemble, the FP32-bulk
+stage, the adjoint workload (adjoint/forward time, finite-difference and
+oracle-reference checks of the gradient) and the CPU oracle baseline.
+
 python bench.py --copy-calibration MIB
 runs a plain device-to-device copy of MIB MiB three times (the known-size
 kernel against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled) and exits.
@@ -183,6 +187,86 @@ def batched(af, I, args):
                       "2x2 Gauss cell averages"}
 
 
+ADJ_REFERENCE = os.path.join(ROOT, "tests", "golden", "adjoint_reference_alfven_perturbed_256.json")
+
+
+def adjoint(af, I, args):
+    """The adjoint workload: gradient of J = 1/2 sum (rho(T) - 1)^2 with
+    respect to all 32 initial planes of the perturbed Alfven wave (256^2,
+    kappa 1, 400 SSP-RK3 steps), sqrt(n) checkpointing (every 20 steps), dt
+    sequence frozen.  Reports adjoint/forward time, central differences
+    (h = 1e-6) on 20 seeded directions and, when present, the FP64 CPU
+    reference (tangent oracle) along 8 directions with the oracle's dts."""
+    import numpy as np
+    import torch
+
+    prob = I.alfven_perturbed(256)
+    nsteps, every = I.ADJOINT_STEPS, 20
+    u0 = I.sample(prob)
+    u0d = af.to_device(u0)
+
+    def J_of(uT):
+        return 0.5 * float(torch.sum((uT[0][0] - I.adjoint_objective_target(prob)) ** 2))
+
+    def grad(dts=None):
+        run = af.CheckpointedRun(prob, every=every)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        ev[0].record(run.ctx.stream)
+        uT = run.forward(u0d, nsteps, dts=dts)
+        ev[1].record(run.ctx.stream)
+        lam = tuple(torch.zeros_like(t) for t in uT)
+        lam[0][0].copy_(uT[0][0] - I.adjoint_objective_target(prob))
+        g = run.backward(lam)
+        ev[2].record(run.ctx.stream)
+        torch.cuda.synchronize()
+        used = run.dts.clone()
+        tape_bytes = run.adj.tape_bytes
+        run.close()
+        return af.to_host(g), used, ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), J_of(uT), tape_bytes
+
+    def J_fixed(u, dts):
+        run = af.CheckpointedRun(prob, every=nsteps)
+        uT = run.forward(af.to_device(u), nsteps, dts=dts)
+        torch.cuda.synchronize()
+        run.close()
+        return J_of(uT)
+
+    grad()  # warm-up (kernel loading, allocator)
+    g, dts, fwd_ckpt_ms, bwd_ms, J, tape_bytes = grad()
+    # the plain forward: 400 whole steps of the stage kernels, no checkpoints
+    ctx = af.Context(prob)
+    u = af.to_device(u0)
+    fwd_ms = timed_steps(ctx, u, nsteps, ctx.stream)
+    ctx.close()
+    # central differences on 20 seeded directions, same dt sequence
+    h = 1e-6
+    errs = []
+    for v in I.adjoint_directions(prob, 20):
+        got = sum(float(np.sum(a * b)) for a, b in zip(g, v))
+        fd = (J_fixed(tuple(a + h * b for a, b in zip(u0, v)), dts)
+              - J_fixed(tuple(a - h * b for a, b in zip(u0, v)), dts)) / (2 * h)
+        errs.append(abs(got - fd) / abs(fd))
+    out = {"workload": f"alfven_perturbed {prob.nx}x{prob.ny}, kappa {prob.kappa}, {nsteps} steps",
+           "objective": "J = 1/2 sum (rho(T) - 1)^2, gradient w.r.t. all 32 initial planes",
+           "forward_ms": fwd_ms, "forward_with_checkpoints_ms": fwd_ckpt_ms, "backward_ms": bwd_ms,
+           "adjoint_over_forward": (fwd_ckpt_ms + bwd_ms) / fwd_ms,
+           "checkpoint_every": every, "checkpoints": (nsteps + every - 1) // every,
+           "tape_bytes_per_stage": tape_bytes, "J": J,
+           "fd": {"directions": 20, "h": h, "max_rel": max(errs), "median_rel": float(np.median(errs))}}
+    if os.path.exists(ADJ_REFERENCE):
+        with open(ADJ_REFERENCE) as fh:
+            ref = json.load(fh)
+        g2, _, _, _, J2, _ = grad(dts=torch.tensor(ref["dts"], dtype=torch.float64, device="cuda"))
+        rel = []
+        for v, want in zip(I.adjoint_directions(prob, len(ref["dJ"])), ref["dJ"]):
+            got = sum(float(np.sum(a * b)) for a, b in zip(g2, v))
+            rel.append(abs(got - want) / abs(want))
+        out["oracle_reference"] = {"directions": len(rel), "max_rel": max(rel), "median_rel": float(np.median(rel)),
+                                   "J_rel": abs(J2 - ref["J"]) / ref["J"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +276,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint measurement (its JSON object)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched-ensemble measurement (its JSON object), e.g. for profiling it")
     ap.add_argument("--save-tile-table", default="", metavar="PATH",
@@ -210,6 +296,9 @@ def main():
 
     if args.batch_only:
         print(json.dumps({"batched": batched(af, I, args)}))
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint(af, I, args)}))
         return
 
     prob = I.CONFIGS[args.workload]()
@@ -313,6 +402,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched(af, I, args)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint(af, I, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, u0)
     print(json.dumps(out))
