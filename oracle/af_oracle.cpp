@@ -1119,6 +1119,51 @@ int orc_t_run(const orc_params* p, int nsteps, const double* dts, double* const*
   for (int q = 0; q < 4; ++q) unpack(s0[q], u[q], du[q]);
   return 0;
 }
+// Limiter building blocks with derivatives (for function-level checks of
+// the adjoint).  Derivative arrays are [ORC_TANGENT][n] for n inputs.
+static Vec tvec(const double* v, const double* d, int n, int off) {
+  Vec u;
+  for (int c = 0; c < NV; ++c) {
+    u[c] = real(v[off + c]);
+    for (int q = 0; q < tangent::ND; ++q) u[c].d[q] = d[(size_t)q * n + off + c];
+  }
+  return u;
+}
+
+// Point scaling limiter: UH, UL (8 each) -> out (8).
+void orc_t_point_limiter(const double* UH, const double* dUH, const double* UL, const double* dUL, double gamma,
+                         double* out, double* dout, int64_t* n_fallback) {
+  Counters c;
+  const Vec w = point_scaling_limiter(tvec(UH, dUH, NV, 0), tvec(UL, dUL, NV, 0), gamma, c);
+  for (int k = 0; k < NV; ++k) {
+    out[k] = w[k].v;
+    for (int q = 0; q < tangent::ND; ++q) dout[(size_t)q * NV + k] = w[k].d[q];
+  }
+  if (n_fallback) *n_fallback = c.n_fallback;
+}
+
+// Flux limiter steps (1)-(2) for one cell: inputs A (8), F (8 x 8: FsL, FsR,
+// FsD, FsU, FlL, FlR, FlD, FlU), S (2 x 8: S_s, S_llf), packed as one
+// vector x[88] with derivatives dx[ND][88] -> theta_src, Lambda[4].
+void orc_t_cell_limiter(const double* x, const double* dx_, double dt, double dx, double dy, double gamma,
+                        double* th, double* dth, double* Lam, double* dLam, int64_t* n_fallback) {
+  const int n = 88;
+  CellWork w;
+  w.A = tvec(x, dx_, n, 0);
+  Vec* fs[8] = {&w.FsL, &w.FsR, &w.FsD, &w.FsU, &w.FlL, &w.FlR, &w.FlD, &w.FlU};
+  for (int k = 0; k < 8; ++k) *fs[k] = tvec(x, dx_, n, 8 + 8 * k);
+  w.S_s = tvec(x, dx_, n, 72);
+  w.S_llf = tvec(x, dx_, n, 80);
+  Counters c;
+  cell_limiter(w, dt, dx, dy, gamma, c);
+  *th = w.theta_src.v;
+  for (int q = 0; q < tangent::ND; ++q) dth[q] = w.theta_src.d[q];
+  for (int I = 0; I < 4; ++I) {
+    Lam[I] = w.Lambda[I].v;
+    for (int q = 0; q < tangent::ND; ++q) dLam[(size_t)q * 4 + I] = w.Lambda[I].d[q];
+  }
+  if (n_fallback) *n_fallback = c.n_fallback;
+}
 #else
 // out = a_k Un + b_k FE(Uk) with (a,b) = (0,1), (3/4,1/4), (1/3,2/3).
 // Each state is given as 4 pointers: cell, xface, yface, vert.

@@ -338,6 +338,10 @@ def tlib():
         L.orc_t_stage.restype = ctypes.c_int
         L.orc_t_run.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _D, _DD, _DD]
         L.orc_t_run.restype = ctypes.c_int
+        I64 = ctypes.POINTER(ctypes.c_int64)
+        L.orc_t_point_limiter.argtypes = [_D, _D, _D, _D, ctypes.c_double, _D, _D, I64]
+        L.orc_t_cell_limiter.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         _D, _D, _D, _D, I64]
         assert L.orc_t_nd() == TANGENT_ND
         _tlib = L
     return _tlib
@@ -392,3 +396,31 @@ def tangent_run(prob, u, du, dts, nthreads: int = 0):
             if lo + d < len(du):
                 douts.append(tuple(np.ascontiguousarray(x[d]) for x in t))
     return v, douts
+
+
+def tangent_point_limiter(uh, ul, gamma, duh, dul):
+    """Point scaling limiter with derivatives along up to TANGENT_ND
+    directions: duh, dul are (n, 8).  Returns (out[8], dout[n, 8], n_fallback)."""
+    n = len(duh)
+    assert n <= TANGENT_ND
+    D1 = np.zeros((TANGENT_ND, 8)); D1[:n] = duh
+    D2 = np.zeros((TANGENT_ND, 8)); D2[:n] = dul
+    out, dout, nf = np.zeros(8), np.zeros((TANGENT_ND, 8)), ctypes.c_int64(0)
+    tlib().orc_t_point_limiter(_ptr(_vec(uh)), _ptr(D1), _ptr(_vec(ul)), _ptr(D2), gamma, _ptr(out), _ptr(dout),
+                               ctypes.byref(nf))
+    return out, dout[:n], nf.value
+
+
+def tangent_cell_limiter(x, dx_dirs, dt, dx, dy, gamma):
+    """Flux limiter steps (1)-(2) of one cell with derivatives.  x[88] =
+    A, FsL, FsR, FsD, FsU, FlL, FlR, FlD, FlU, S_s, S_llf (8 each);
+    dx_dirs (n, 88).  Returns (theta_src, dtheta[n], Lambda[4], dLambda[n, 4], n_fallback)."""
+    n = len(dx_dirs)
+    assert n <= TANGENT_ND
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    D = np.zeros((TANGENT_ND, 88)); D[:n] = dx_dirs
+    th, lam = ctypes.c_double(0.0), np.zeros(4)
+    dth, dlam, nf = np.zeros(TANGENT_ND), np.zeros((TANGENT_ND, 4)), ctypes.c_int64(0)
+    tlib().orc_t_cell_limiter(_ptr(x), _ptr(D), dt, dx, dy, gamma, ctypes.byref(th), _ptr(dth), _ptr(lam),
+                              _ptr(dlam), ctypes.byref(nf))
+    return th.value, dth[:n], lam, dlam[:n], nf.value

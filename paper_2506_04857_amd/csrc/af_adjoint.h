@@ -41,6 +41,9 @@
 #ifndef AF_HD
 #define AF_HD __host__ __device__ inline
 #endif
+#ifndef AF_NOINLINE
+#define AF_NOINLINE __host__ __device__ __attribute__((noinline))
+#endif
 
 namespace afadj {
 
@@ -836,6 +839,11 @@ enum : uint64_t {
   // bits 55..58: Lambda_I floored at 0 by the shifted fallback
   // bits 59..60: interface of the smallest sensor coefficient (L, R, D, U)
 };
+// Bits under which some coefficient of steps (1)-(2) depends on the state
+// (source fraction or its fallback, a density-box fraction, a vertex root,
+// the box fallback); without them theta_src = Lambda_I = 1 are constants.
+constexpr uint64_t LM_ACTIVE = LM_TSRC | LM_TS_SHIFT | LM_TS_ZERO | (15ull << 10) | (0x7fffull << 18) |
+                               LM_BOX_SHIFT | LM_BOX_ZERO;
 AF_HD uint64_t lm_lrf(int I) { return 1ull << (10 + I); }
 AF_HD uint64_t lm_neg(int I) { return 1ull << (14 + I); }
 AF_HD uint64_t lm_root(int k) { return 1ull << (17 + k); }
@@ -1078,8 +1086,8 @@ struct CellAdj {
   double Fs[4][NV], Fl[4][NV];
   double Ss[NV], Sllf[NV];
 };
-AF_HD void cell_limiter_vjp(const CellIn& w, double dt, const AGeo& g, const double* rk, uint64_t fl, double lthsrc,
-                            const double* lLam, CellAdj& o) {
+AF_NOINLINE void cell_limiter_vjp(const CellIn& w, double dt, const AGeo& g, const double* rk, uint64_t fl,
+                                  double lthsrc, const double* lLam, CellAdj& o) {
   const double gm = g.gamma;
   const double ldx = dt / g.dx, ldy = dt / g.dy;
   double Allf[NV], Asrc[NV];

@@ -148,6 +148,19 @@ struct StateM {
   double *a, *x, *y, *v;
 };
 
+// A stencil slot of the reverse sweep: where a state is read and where its
+// adjoint is added (the centre values come from the tape, their adjoints go
+// to the workspace buffer).
+struct Slot {
+  const double* src;
+  double* dst;
+  Loc L;
+};
+template <class Add>
+AF_HD void slot_put(const Slot& q, const double* l) {
+  put<Add>(q.dst, q.L, l);
+}
+
 AF_HD void ldC(const AGeo& g, const Tape& t, int i, int j, double* u) {
   const size_t id = (size_t)mcell(j, g.ny, g.bcy) * g.nx + mcell(i, g.nx, g.bcx);
   for (int c = 0; c < NV; ++c) u[c] = t.C[id + c * (size_t)g.nx * g.ny];
@@ -550,10 +563,67 @@ AF_HD void adj_update(const AGeo& g, const Tape& t, const AdjBuf& ab, const Stat
   add8<Add>(ab.lSll, eid, en, lSl);
 }
 
-// Limiter cell (i, j), extended range.
+// The nine points of cell (i, j) as slots (a along x, b along y).
+AF_HD void nine_slots(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateM& lk, int i, int j,
+                      Slot q[3][3]) {
+  q[0][0] = Slot{u.v, lk.v, locV(g, i, j)};
+  q[1][0] = Slot{u.y, lk.y, locY(g, i, j)};
+  q[2][0] = Slot{u.v, lk.v, locV(g, i + 1, j)};
+  q[0][1] = Slot{u.x, lk.x, locX(g, i, j)};
+  q[1][1] = Slot{t.C, ab.lC, locA(g, i, j)};
+  q[2][1] = Slot{u.x, lk.x, locX(g, i + 1, j)};
+  q[0][2] = Slot{u.v, lk.v, locV(g, i, j + 1)};
+  q[1][2] = Slot{u.y, lk.y, locY(g, i, j + 1)};
+  q[2][2] = Slot{u.v, lk.v, locV(g, i + 1, j + 1)};
+}
+// Reverse of the nine-point source, one point at a time: pass 1 forms the
+// nine div B values from the normal field components and the adjoints of
+// the nine div B's (which need Psi at each point); pass 2 scatters each
+// point's adjoint once (its Psi part plus its share of every div B).
 template <class Add>
-AF_HD void adj_limiter(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateM& lk, int i, int j,
-                       double dt) {
+AF_HD void source_reverse(const AGeo& g, const Slot q[3][3], const double* lS) {
+  const double w[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+  double B1[3][3], B2[3][3], dv[3][3], ldv[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      B1[a][b] = q[a][b].src[q[a][b].L.i + 4 * q[a][b].L.s];
+      B2[a][b] = q[a][b].src[q[a][b].L.i + 5 * q[a][b].L.s];
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      dv[a][b] = d3(a, B1[0][b], B1[1][b], B1[2][b]) / g.dx + d3(b, B2[a][0], B2[a][1], B2[a][2]) / g.dy;
+      double U[NV], Q[NV];
+      ld(q[a][b].src, q[a][b].L, U);
+      psi(U, Q);
+      double s = 0.0;
+      for (int c = 0; c < NV; ++c) s += w[a] * w[b] * lS[c] * Q[c];
+      ldv[a][b] = s;
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double U[NV], lQ[NV], lU[NV];
+      ld(q[a][b].src, q[a][b].L, U);
+      for (int c = 0; c < NV; ++c) lQ[c] = w[a] * w[b] * dv[a][b] * lS[c];
+      zero8(lU);
+      psi_vjp(U, lQ, lU);
+      // this point is entry a of row b (B1 derivatives) and entry b of column a (B2)
+      double l4 = 0.0, l5 = 0.0;
+      for (int p = 0; p < 3; ++p) {
+        l4 += d3c(p, a) * ldv[p][b] / g.dx;
+        l5 += d3c(p, b) * ldv[a][p] / g.dy;
+      }
+      lU[4] += l4;
+      lU[5] += l5;
+      slot_put<Add>(q[a][b], lU);
+    }
+}
+
+// Reverse of steps (1)-(2) of a limiter cell whose coefficients depend on
+// the state (out of line: rare).  Scatters the adjoints of A and of the
+// four interfaces' fluxes, and adds those of Ss, Sllf to oSs, oSll.
+template <class Add>
+AF_NOINLINE void limiter_active_vjp(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateM& lk,
+                                    int i, int j, double dt, uint64_t fl, double* oSs, double* oSll) {
   const Ext e = ext_of(g);
   const size_t eid = eidx(e, i, j), en = (size_t)e.ew * e.eh;
   CellIn w;
@@ -563,45 +633,65 @@ AF_HD void adj_limiter(const AGeo& g, const StateC& u, const Tape& t, const AdjB
   double ts[4];
   for (int I = 0; I < 4; ++I) ld_iface(r[I], w.Fs[I], w.Fl[I], ts[I]);
   cell_sources(e, t, i, j, ts, w.Ss, w.Sllf);
-  const uint64_t fl = t.lfl[eid];
   double rk[15], lLam[4];
   for (int k = 0; k < 15; ++k) rk[k] = t.rk[eid + k * en];
   for (int I = 0; I < 4; ++I) lLam[I] = ab.lLam[eid + I * en];
   CellAdj o;
   zero8(o.A);
+  zero8(o.Ss);
+  zero8(o.Sllf);
   for (int I = 0; I < 4; ++I) {
     zero8(o.Fs[I]);
     zero8(o.Fl[I]);
   }
-  ld8(ab.lSs, eid, en, o.Ss);
-  ld8(ab.lSll, eid, en, o.Sllf);
   cell_limiter_vjp(w, dt, g, rk, fl, ab.lth[eid], lLam, o);
   for (int I = 0; I < 4; ++I) {
     add8<Add>(I < 2 ? ab.xlFs : ab.ylFs, r[I].id, r[I].n, o.Fs[I]);
     add8<Add>(I < 2 ? ab.xlFl : ab.ylFl, r[I].id, r[I].n, o.Fl[I]);
   }
-  // Ss = tsc S + (1 - tsc) Sllf
-  double S[NV], lS[NV];
-  ld8(t.S, eid, en, S);
-  const int am = lm_tsmin(fl);
-  const double tsc = ts[am];
-  double ltsc = 0.0;
+  put<Add>(lk.a, locA(g, i, j), o.A);
   for (int c = 0; c < NV; ++c) {
-    ltsc += o.Ss[c] * (S[c] - w.Sllf[c]);
-    lS[c] = tsc * o.Ss[c];
-    o.Sllf[c] += (1.0 - tsc) * o.Ss[c];
+    oSs[c] += o.Ss[c];
+    oSll[c] += o.Sllf[c];
   }
-  if (ltsc != 0.0) Add::add((am < 2 ? ab.xlts : ab.ylts) + r[am].id, ltsc);
+}
+
+// Limiter cell (i, j), extended range.
+template <class Add>
+AF_HD void adj_limiter(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateM& lk, int i, int j,
+                       double dt) {
+  const Ext e = ext_of(g);
+  const size_t eid = eidx(e, i, j), en = (size_t)e.ew * e.eh;
+  const uint64_t fl = t.lfl[eid];
+  double oSs[NV], oSll[NV];
+  ld8(ab.lSs, eid, en, oSs);
+  ld8(ab.lSll, eid, en, oSll);
+  if (fl & LM_ACTIVE) limiter_active_vjp<Add>(g, u, t, ab, lk, i, j, dt, fl, oSs, oSll);
+  // Ss = tsc S + (1 - tsc) Sllf, tsc the smallest sensor coefficient of the cell
+  const int am = lm_tsmin(fl);
+  const IfaceRef r = iref(e, t, am < 2 ? 0 : 1, am == 1 ? i + 1 : i, am == 3 ? j + 1 : j);
+  const double tsc = r.ts[r.id];
+  double S[NV], Sllf[NV], lS[NV], ltsc = 0.0;
+  ld8(t.S, eid, en, S);
+  ld8(t.Sllf, eid, en, Sllf);
+  for (int c = 0; c < NV; ++c) {
+    ltsc += oSs[c] * (S[c] - Sllf[c]);
+    lS[c] = tsc * oSs[c];
+    oSll[c] += (1.0 - tsc) * oSs[c];
+  }
+  if (ltsc != 0.0) Add::add((am < 2 ? ab.xlts : ab.ylts) + r.id, ltsc);
   // Sllf = div Bbar Psi(A)
-  double Q[NV], lQ[NV], ldiv = 0.0;
-  psi(w.A, Q);
+  double A[NV], Q[NV], lQ[NV], lA[NV], ldiv = 0.0;
+  ld(u.a, locA(g, i, j), A);
+  psi(A, Q);
   const double divb = div_bbar(g, u, i, j);
   for (int c = 0; c < NV; ++c) {
-    ldiv += o.Sllf[c] * Q[c];
-    lQ[c] = divb * o.Sllf[c];
+    ldiv += oSll[c] * Q[c];
+    lQ[c] = divb * oSll[c];
   }
-  psi_vjp(w.A, lQ, o.A);
-  put<Add>(lk.a, locA(g, i, j), o.A);
+  zero8(lA);
+  psi_vjp(A, lQ, lA);
+  put<Add>(lk.a, locA(g, i, j), lA);
   if (ldiv != 0.0) {
     const Loc Lr = locA(g, i + 1, j), Ll = locA(g, i - 1, j), Lu = locA(g, i, j + 1), Ld = locA(g, i, j - 1);
     Add::add(lk.a + Lr.i + 4 * Lr.s, ldiv / (2.0 * g.dx));
@@ -609,23 +699,13 @@ AF_HD void adj_limiter(const AGeo& g, const StateC& u, const Tape& t, const AdjB
     Add::add(lk.a + Lu.i + 5 * Lu.s, ldiv / (2.0 * g.dy));
     Add::add(lk.a + Ld.i + 5 * Ld.s, -ldiv / (2.0 * g.dy));
   }
-  // high-order source on the nine points
-  double P[3][3][NV], lP[3][3][NV];
-  nine_points(g, u, t, i, j, P);
-  for (int p = 0; p < 3; ++p)
-    for (int q = 0; q < 3; ++q) zero8(lP[p][q]);
-  const double* pp[3][3] = {{P[0][0], P[0][1], P[0][2]}, {P[1][0], P[1][1], P[1][2]}, {P[2][0], P[2][1], P[2][2]}};
-  double* lpp[3][3] = {{lP[0][0], lP[0][1], lP[0][2]}, {lP[1][0], lP[1][1], lP[1][2]}, {lP[2][0], lP[2][1], lP[2][2]}};
-  cell_source_vjp(pp, g, lS, lpp);
-  put<Add>(lk.v, locV(g, i, j), lP[0][0]);
-  put<Add>(lk.y, locY(g, i, j), lP[1][0]);
-  put<Add>(lk.v, locV(g, i + 1, j), lP[2][0]);
-  put<Add>(lk.x, locX(g, i, j), lP[0][1]);
-  putC<Add>(g, ab.lC, i, j, lP[1][1]);
-  put<Add>(lk.x, locX(g, i + 1, j), lP[2][1]);
-  put<Add>(lk.v, locV(g, i, j + 1), lP[0][2]);
-  put<Add>(lk.y, locY(g, i, j + 1), lP[1][2]);
-  put<Add>(lk.v, locV(g, i + 1, j + 1), lP[2][2]);
+  bool any = false;
+  for (int c = 0; c < NV; ++c) any = any || lS[c] != 0.0;
+  if (any) {
+    Slot q[3][3];
+    nine_slots(g, u, t, ab, lk, i, j, q);
+    source_reverse<Add>(g, q, lS);
+  }
 }
 
 // Interface, extended range.
@@ -662,7 +742,9 @@ AF_HD void adj_iface(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf
   flux_vjp(p[0], g.gamma, dir, lh, l0);
   flux_vjp(p[1], g.gamma, dir, lh4, l1);
   flux_vjp(p[2], g.gamma, dir, lh, l2);
-  llf_vjp(Al, Ar, g.gamma, dir, lFl, lAl, lAr);
+  bool anyl = false;
+  for (int c = 0; c < NV; ++c) anyl = anyl || lFl[c] != 0.0;
+  if (anyl) llf_vjp(Al, Ar, g.gamma, dir, lFl, lAl, lAr);
   if (dir == 0) {
     put<Add>(lk.v, locV(g, k, j), l0);
     put<Add>(lk.x, locX(g, k, j), l1);
@@ -714,6 +796,116 @@ AF_HD void adj_sensor(const AGeo& g, const StateC& u, const Tape& t, const AdjBu
   put<Add>(lk.a, locA(g, i, j + 1), l[4]);
 }
 
+// The FVS lines and central pair of a point.  kind 0: X(k,l) (x line, y
+// pair V(k,l), V(k,l+1)); 1: Y(k,l) (y line, x pair V(k,l), V(k+1,l));
+// 2: V(k,l) (both lines).
+AF_HD void point_slots(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateM& lk, int kind,
+                       int k, int l, Slot lx[5], Slot ly[5], Slot pair[2]) {
+  auto X = [&](int a, int b) { return Slot{u.x, lk.x, locX(g, a, b)}; };
+  auto Y = [&](int a, int b) { return Slot{u.y, lk.y, locY(g, a, b)}; };
+  auto V = [&](int a, int b) { return Slot{u.v, lk.v, locV(g, a, b)}; };
+  auto C = [&](int a, int b) { return Slot{t.C, ab.lC, locA(g, a, b)}; };
+  if (kind == 0) {
+    lx[0] = X(k - 1, l); lx[1] = C(k - 1, l); lx[2] = X(k, l); lx[3] = C(k, l); lx[4] = X(k + 1, l);
+    pair[0] = V(k, l); pair[1] = V(k, l + 1);
+  } else if (kind == 1) {
+    ly[0] = Y(k, l - 1); ly[1] = C(k, l - 1); ly[2] = Y(k, l); ly[3] = C(k, l); ly[4] = Y(k, l + 1);
+    pair[0] = V(k, l); pair[1] = V(k + 1, l);
+  } else {
+    lx[0] = V(k - 1, l); lx[1] = Y(k - 1, l); lx[2] = V(k, l); lx[3] = Y(k, l); lx[4] = V(k + 1, l);
+    ly[0] = V(k, l - 1); ly[1] = X(k, l - 1); ly[2] = V(k, l); ly[3] = X(k, l); ly[4] = V(k, l + 1);
+  }
+}
+// Pass 1 over an FVS line: alpha (largest spectral radius, first on ties),
+// its slot, and 1/2 (D+ B_n + D- B_n).
+AF_HD void line_scan(const Slot q[5], double gm, int n, double h, double& alpha, int& am, double& dB) {
+  alpha = 0.0;
+  am = -1;
+  double b[5];
+  for (int m = 0; m < 5; ++m) {
+    double w[NV];
+    ld(q[m].src, q[m].L, w);
+    const double r = srad(w, gm, n);
+    if (alpha < r) {
+      alpha = r;
+      am = m;
+    }
+    b[m] = w[4 + n];
+  }
+  dB = 0.5 * ((b[0] - 4.0 * b[1] + 3.0 * b[2]) / h + (-3.0 * b[2] + 4.0 * b[3] - b[4]) / h);
+}
+// Passes 2 and 3: the reverse of R = sum_m [sp_m F(w_m) + sd_m alpha w_m]
+// and of dB, one state at a time, then of alpha at its argmax.
+template <class Add>
+AF_HD void line_reverse(const Slot q[5], double gm, int n, double h, double alpha, int am, const double* lR,
+                        double ldB) {
+  const double cp[5] = {1.0, -4.0, 3.0, 0.0, 0.0};
+  const double cm[5] = {0.0, 0.0, -3.0, 4.0, -1.0};
+  double lal = 0.0;
+  for (int m = 0; m < 5; ++m) {
+    const double sp = 0.5 * (cp[m] + cm[m]) / h, sd = 0.5 * (cp[m] - cm[m]) / h;
+    double w[NV], lF[NV], lw[NV];
+    ld(q[m].src, q[m].L, w);
+    for (int c = 0; c < NV; ++c) {
+      lF[c] = sp * lR[c];
+      lw[c] = sd * alpha * lR[c];
+      lal += sd * lR[c] * w[c];
+    }
+    flux_vjp(w, gm, n, lF, lw);
+    lw[4 + n] += sp * ldB;
+    slot_put<Add>(q[m], lw);
+  }
+  if (am >= 0 && lal != 0.0) {
+    double w[NV], lw[NV];
+    ld(q[am].src, q[am].L, w);
+    zero8(lw);
+    srad_vjp(w, gm, n, lal, lw);
+    slot_put<Add>(q[am], lw);
+  }
+}
+
+// Reverse of a point's scaling limiter and first-order LLF state where the
+// limiter acted (out of line: rare, and it would set the register budget of
+// the common path).  Writes the adjoint of U^H to lH and scatters the LLF
+// state's adjoints.
+template <class Add>
+AF_NOINLINE void point_limited_vjp(const AGeo& g, const StateC& u, const Tape& t, const StateM& lk, int kind, int k,
+                                   int l, double dt, uint32_t fl, const double* lam, double* lH) {
+  PointSt s;
+  point_stencil(g, u, t, kind, k, l, s);
+  double H[NV], Lf[NV], lLf[NV], lU[NV], lL[NV], lR[NV], lD[NV], lUp[NV];
+  point_high(g, kind, s, dt, H);
+  point_llf(s.U, s.L, s.R, s.D, s.Up, dt, g, Lf);
+  zero8(lH);
+  zero8(lLf);
+  point_limit_vjp(H, Lf, g.gamma, fl, lam, lH, lLf);
+  zero8(lU);
+  zero8(lL);
+  zero8(lR);
+  zero8(lD);
+  zero8(lUp);
+  point_llf_vjp(s.U, s.L, s.R, s.D, s.Up, dt, g, lLf, lU, lL, lR, lD, lUp);
+  if (kind == 0) {
+    put<Add>(lk.x, locX(g, k, l), lU);
+    put<Add>(lk.x, locX(g, k - 1, l), lL);
+    put<Add>(lk.x, locX(g, k + 1, l), lR);
+    put<Add>(lk.v, locV(g, k, l), lD);
+    put<Add>(lk.v, locV(g, k, l + 1), lUp);
+  } else if (kind == 1) {
+    put<Add>(lk.y, locY(g, k, l), lU);
+    put<Add>(lk.v, locV(g, k, l), lL);
+    put<Add>(lk.v, locV(g, k + 1, l), lR);
+    put<Add>(lk.y, locY(g, k, l - 1), lD);
+    put<Add>(lk.y, locY(g, k, l + 1), lUp);
+  } else {
+    put<Add>(lk.v, locV(g, k, l), lU);
+    put<Add>(lk.v, locV(g, k - 1, l), lL);
+    put<Add>(lk.v, locV(g, k + 1, l), lR);
+    put<Add>(lk.v, locV(g, k, l - 1), lD);
+    put<Add>(lk.v, locV(g, k, l + 1), lUp);
+  }
+}
+
 // Point of kind (0 X, 1 Y, 2 V), real.
 template <class Add>
 AF_HD void adj_point(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateC& lo, const StateM& ln,
@@ -730,115 +922,55 @@ AF_HD void adj_point(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf
     any = any || lam[c] != 0.0;
   }
   if (!any) return;
-  PointSt s;
-  point_stencil(g, u, t, kind, k, l, s);
-  double H[NV], Lf[NV];
-  point_high(g, kind, s, dt, H);
-  point_llf(s.U, s.L, s.R, s.D, s.Up, dt, g, Lf);
-  double lH[NV], lLf[NV];
-  zero8(lH);
-  zero8(lLf);
-  point_limit_vjp(H, Lf, g.gamma, t.pfl[kind][id], lam, lH, lLf);
-  // first-order part
-  double lU[NV], lL[NV], lR[NV], lD[NV], lUp[NV];
-  zero8(lU);
-  zero8(lL);
-  zero8(lR);
-  zero8(lD);
-  zero8(lUp);
-  point_llf_vjp(s.U, s.L, s.R, s.D, s.Up, dt, g, lLf, lU, lL, lR, lD, lUp);
-  // high-order part: H = U + dt (-R1 - R2 - div B Psi(U))
-  double R1[NV], R2[NV], d1 = 0.0, d2 = 0.0, P[NV];
-  const double* wx[5] = {s.wx[0], s.wx[1], s.wx[2], s.wx[3], s.wx[4]};
-  const double* wy[5] = {s.wy[0], s.wy[1], s.wy[2], s.wy[3], s.wy[4]};
-  if (kind != 1) fvs_line(wx, g.gamma, 0, g.dx, R1, d1);
-  if (kind != 0) fvs_line(wy, g.gamma, 1, g.dy, R2, d2);
-  if (kind == 0) d2 = (s.cb[5] - s.ca[5]) / g.dy;
-  if (kind == 1) d1 = (s.cb[4] - s.ca[4]) / g.dx;
+  const uint32_t fl = t.pfl[kind][id];
+  double lH[NV];
+  if (fl & (BL_T1 | BL_T2 | BL_SHIFT | BL_ZERO))
+    point_limited_vjp<Add>(g, u, t, lk, kind, k, l, dt, fl, lam, lH);
+  else
+    for (int c = 0; c < NV; ++c) lH[c] = lam[c];  // limiter inactive: the output is U^H
+  // H = U + dt (-R1 - R2 - div B Psi(U))
+  Slot lx[5], ly[5], pair[2];
+  point_slots(g, u, t, ab, lk, kind, k, l, lx, ly, pair);
+  double ax = 0.0, ay = 0.0, d1 = 0.0, d2 = 0.0;
+  int mx = -1, my = -1;
+  if (kind != 1) line_scan(lx, g.gamma, 0, g.dx, ax, mx, d1);
+  if (kind != 0) line_scan(ly, g.gamma, 1, g.dy, ay, my, d2);
+  if (kind == 0) d2 = (pair[1].src[pair[1].L.i + 5 * pair[1].L.s] - pair[0].src[pair[0].L.i + 5 * pair[0].L.s]) / g.dy;
+  if (kind == 1) d1 = (pair[1].src[pair[1].L.i + 4 * pair[1].L.s] - pair[0].src[pair[0].L.i + 4 * pair[0].L.s]) / g.dx;
   const double divB = d1 + d2;
-  psi(s.U, P);
-  double lR1[NV], lP[NV], ldiv = 0.0;
-  for (int c = 0; c < NV; ++c) {
-    lU[c] += lH[c];
-    lR1[c] = -dt * lH[c];
-    ldiv -= dt * lH[c] * P[c];
-    lP[c] = -dt * divB * lH[c];
-  }
-  psi_vjp(s.U, lP, lU);
-  double lwx[5][NV], lwy[5][NV], lca[NV], lcb[NV];
-  for (int m = 0; m < 5; ++m) {
-    zero8(lwx[m]);
-    zero8(lwy[m]);
-  }
-  zero8(lca);
-  zero8(lcb);
-  double* lwxp[5] = {lwx[0], lwx[1], lwx[2], lwx[3], lwx[4]};
-  double* lwyp[5] = {lwy[0], lwy[1], lwy[2], lwy[3], lwy[4]};
-  if (kind != 1) fvs_line_vjp(wx, g.gamma, 0, g.dx, lR1, ldiv, lwxp);
-  if (kind != 0) fvs_line_vjp(wy, g.gamma, 1, g.dy, lR1, ldiv, lwyp);
-  if (kind == 0) {  // central F2 between V(k,j) and V(k,j+1)
-    double lFu[NV], lFd[NV];
+  {
+    double U[NV], P[NV], lP[NV], lU[NV];
+    const Loc LU = kind == 0 ? locX(g, k, l) : kind == 1 ? locY(g, k, l) : locV(g, k, l);
+    const double* src = kind == 0 ? u.x : kind == 1 ? u.y : u.v;
+    ld(src, LU, U);
+    psi(U, P);
+    double ldiv = 0.0;
     for (int c = 0; c < NV; ++c) {
-      lFu[c] = lR1[c] / g.dy;
-      lFd[c] = -lR1[c] / g.dy;
+      lU[c] = lH[c];
+      ldiv -= dt * lH[c] * P[c];
+      lP[c] = -dt * divB * lH[c];
     }
-    flux_vjp(s.cb, g.gamma, 1, lFu, lcb);
-    flux_vjp(s.ca, g.gamma, 1, lFd, lca);
-    lcb[5] += ldiv / g.dy;
-    lca[5] -= ldiv / g.dy;
-  } else if (kind == 1) {  // central F1 between V(i,l) and V(i+1,l)
-    double lFr[NV], lFl[NV];
-    for (int c = 0; c < NV; ++c) {
-      lFr[c] = lR1[c] / g.dx;
-      lFl[c] = -lR1[c] / g.dx;
+    psi_vjp(U, lP, lU);
+    put<Add>(kind == 0 ? lk.x : kind == 1 ? lk.y : lk.v, LU, lU);
+    double lR[NV];
+    for (int c = 0; c < NV; ++c) lR[c] = -dt * lH[c];
+    if (kind != 1) line_reverse<Add>(lx, g.gamma, 0, g.dx, ax, mx, lR, ldiv);
+    if (kind != 0) line_reverse<Add>(ly, g.gamma, 1, g.dy, ay, my, lR, ldiv);
+    if (kind != 2) {
+      // central pair: R = (F(pair1) - F(pair0)) / h in the transverse direction
+      const int dir = kind == 0 ? 1 : 0;
+      const double h = kind == 0 ? g.dy : g.dx;
+      for (int q = 0; q < 2; ++q) {
+        double w[NV], lF[NV], lw[NV];
+        ld(pair[q].src, pair[q].L, w);
+        const double sgnq = q ? 1.0 : -1.0;
+        for (int c = 0; c < NV; ++c) lF[c] = sgnq * lR[c] / h;
+        zero8(lw);
+        flux_vjp(w, g.gamma, dir, lF, lw);
+        lw[4 + dir] += sgnq * ldiv / h;
+        slot_put<Add>(pair[q], lw);
+      }
     }
-    flux_vjp(s.cb, g.gamma, 0, lFr, lcb);
-    flux_vjp(s.ca, g.gamma, 0, lFl, lca);
-    lcb[4] += ldiv / g.dx;
-    lca[4] -= ldiv / g.dx;
-  }
-  // scatter; the centre slot of each line is the point itself
-  if (kind == 0) {
-    for (int c = 0; c < NV; ++c) lU[c] += lwx[2][c];
-    put<Add>(lk.x, locX(g, k, l), lU);
-    put<Add>(lk.x, locX(g, k - 1, l), lwx[0]);
-    putC<Add>(g, ab.lC, k - 1, l, lwx[1]);
-    putC<Add>(g, ab.lC, k, l, lwx[3]);
-    put<Add>(lk.x, locX(g, k + 1, l), lwx[4]);
-    put<Add>(lk.v, locV(g, k, l), lca);
-    put<Add>(lk.v, locV(g, k, l + 1), lcb);
-    put<Add>(lk.x, locX(g, k - 1, l), lL);
-    put<Add>(lk.x, locX(g, k + 1, l), lR);
-    put<Add>(lk.v, locV(g, k, l), lD);
-    put<Add>(lk.v, locV(g, k, l + 1), lUp);
-  } else if (kind == 1) {
-    for (int c = 0; c < NV; ++c) lU[c] += lwy[2][c];
-    put<Add>(lk.y, locY(g, k, l), lU);
-    put<Add>(lk.y, locY(g, k, l - 1), lwy[0]);
-    putC<Add>(g, ab.lC, k, l - 1, lwy[1]);
-    putC<Add>(g, ab.lC, k, l, lwy[3]);
-    put<Add>(lk.y, locY(g, k, l + 1), lwy[4]);
-    put<Add>(lk.v, locV(g, k, l), lca);
-    put<Add>(lk.v, locV(g, k + 1, l), lcb);
-    put<Add>(lk.v, locV(g, k, l), lL);
-    put<Add>(lk.v, locV(g, k + 1, l), lR);
-    put<Add>(lk.y, locY(g, k, l - 1), lD);
-    put<Add>(lk.y, locY(g, k, l + 1), lUp);
-  } else {
-    for (int c = 0; c < NV; ++c) lU[c] += lwx[2][c] + lwy[2][c];
-    put<Add>(lk.v, locV(g, k, l), lU);
-    put<Add>(lk.v, locV(g, k - 1, l), lwx[0]);
-    put<Add>(lk.y, locY(g, k - 1, l), lwx[1]);
-    put<Add>(lk.y, locY(g, k, l), lwx[3]);
-    put<Add>(lk.v, locV(g, k + 1, l), lwx[4]);
-    put<Add>(lk.v, locV(g, k, l - 1), lwy[0]);
-    put<Add>(lk.x, locX(g, k, l - 1), lwy[1]);
-    put<Add>(lk.x, locX(g, k, l), lwy[3]);
-    put<Add>(lk.v, locV(g, k, l + 1), lwy[4]);
-    put<Add>(lk.v, locV(g, k - 1, l), lL);
-    put<Add>(lk.v, locV(g, k + 1, l), lR);
-    put<Add>(lk.v, locV(g, k, l - 1), lD);
-    put<Add>(lk.v, locV(g, k, l + 1), lUp);
   }
 }
 
@@ -858,7 +990,10 @@ AF_HD void adj_centre(const AGeo& g, const StateC& u, const Tape& t, const AdjBu
   centre_raw(p, Uc);
   zero8(lA);
   zero8(lUc);
-  centre_limit_vjp(in[0], Uc, g.gamma, t.cfl[id], lC, lA, lUc);
+  if (t.cfl[id] & (BL_T1 | BL_T2 | BL_SHIFT | BL_ZERO))
+    centre_limit_vjp(in[0], Uc, g.gamma, t.cfl[id], lC, lA, lUc);
+  else
+    for (int c = 0; c < NV; ++c) lUc[c] = lC[c];  // C = C~
   double lf[NV], lv[NV];
   for (int c = 0; c < NV; ++c) {
     lA[c] += 36.0 / 16.0 * lUc[c];

@@ -10,6 +10,7 @@ using std::exp;
 using std::fabs;
 using std::sqrt;
 #define AF_HD inline
+#define AF_NOINLINE inline
 #include "af_adjoint_stage.h"
 
 using namespace afadj;
@@ -107,6 +108,65 @@ void hc_adjoint(const hc_params* p, int k, const double* const* uk, const void* 
     for (int kk = 0; kk < g.nxp; ++kk) adj_point<HostAdd>(g, u, t, ab, lo, ln, lk, 2, kk, l, dt, a, b);
   for (int j = 0; j < g.ny; ++j)
     for (int i = 0; i < g.nx; ++i) adj_centre<HostAdd>(g, u, t, ab, lk, i, j);
+}
+
+}  // extern "C"
+
+// ---- the limiters alone (function-level checks)
+extern "C" {
+
+void hc_point_limit(const double* UH, const double* UL, double g, double* out, uint32_t* fl) {
+  uint32_t f = 0;
+  point_limit(UH, UL, g, out, f);
+  *fl = f;
+}
+void hc_point_limit_vjp(const double* UH, const double* UL, double g, uint32_t fl, const double* lout, double* lUH,
+                        double* lUL) {
+  for (int c = 0; c < NV; ++c) lUH[c] = lUL[c] = 0.0;
+  point_limit_vjp(UH, UL, g, fl, lout, lUH, lUL);
+}
+static CellIn cell_in(const double* x) {
+  CellIn w;
+  for (int c = 0; c < NV; ++c) {
+    w.A[c] = x[c];
+    for (int I = 0; I < 4; ++I) {
+      w.Fs[I][c] = x[8 + 8 * I + c];
+      w.Fl[I][c] = x[40 + 8 * I + c];
+    }
+    w.Ss[c] = x[72 + c];
+    w.Sllf[c] = x[80 + c];
+  }
+  return w;
+}
+// x[88] = A, FsL..FsU, FlL..FlU, S_s, S_llf
+void hc_cell_limiter(const double* x, double dt, double dx, double dy, double g, double* th, double* Lam, double* rk,
+                     uint64_t* fl) {
+  AGeo geo{};
+  geo.dx = dx;
+  geo.dy = dy;
+  geo.gamma = g;
+  uint64_t f = 0;
+  cell_limiter(cell_in(x), dt, geo, *th, Lam, rk, f);
+  *fl = f;
+}
+void hc_cell_limiter_vjp(const double* x, double dt, double dx, double dy, double g, const double* rk, uint64_t fl,
+                         double lth, const double* lLam, double* lx) {
+  AGeo geo{};
+  geo.dx = dx;
+  geo.dy = dy;
+  geo.gamma = g;
+  CellAdj o;
+  std::memset(&o, 0, sizeof(o));
+  cell_limiter_vjp(cell_in(x), dt, geo, rk, fl, lth, lLam, o);
+  for (int c = 0; c < NV; ++c) {
+    lx[c] = o.A[c];
+    for (int I = 0; I < 4; ++I) {
+      lx[8 + 8 * I + c] = o.Fs[I][c];
+      lx[40 + 8 * I + c] = o.Fl[I][c];
+    }
+    lx[72 + c] = o.Ss[c];
+    lx[80 + c] = o.Sllf[c];
+  }
 }
 
 }  // extern "C"

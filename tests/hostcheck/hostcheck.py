@@ -49,6 +49,12 @@ def lib():
         L.hc_record.argtypes = [ctypes.POINTER(_P), ctypes.c_int, _DD, _DD, _DD, ctypes.c_double, ctypes.c_void_p]
         L.hc_adjoint.argtypes = [ctypes.POINTER(_P), ctypes.c_int, _DD, ctypes.c_void_p, ctypes.c_double, _DD, _DD,
                                  _DD, ctypes.c_void_p]
+        U32, U64 = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)
+        dbl = ctypes.c_double
+        L.hc_point_limit.argtypes = [_D, _D, dbl, _D, U32]
+        L.hc_point_limit_vjp.argtypes = [_D, _D, dbl, ctypes.c_uint32, _D, _D, _D]
+        L.hc_cell_limiter.argtypes = [_D, dbl, dbl, dbl, dbl, _D, _D, _D, U64]
+        L.hc_cell_limiter_vjp.argtypes = [_D, dbl, dbl, dbl, dbl, _D, ctypes.c_uint64, dbl, _D, _D]
         _lib = L
     return _lib
 
@@ -84,3 +90,42 @@ def adjoint(prob, k, uk, tape, dt, lam_out, lam_n=None, lam_k=None):
     lib().hc_adjoint(ctypes.byref(p), k, _ptrs(uk), tape.ctypes.data_as(ctypes.c_void_p), dt, _ptrs(lam_out),
                      _ptrs(lam_n), _ptrs(lam_k), b.ctypes.data_as(ctypes.c_void_p))
     return lam_n, lam_k
+
+
+def _p(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_D)
+
+
+def point_limit(uh, ul, gamma):
+    """(out[8], decision bits)."""
+    (uh, puh), (ul, pul) = _p(uh), _p(ul)
+    out = np.zeros(8)
+    fl = ctypes.c_uint32(0)
+    lib().hc_point_limit(puh, pul, gamma, out.ctypes.data_as(_D), ctypes.byref(fl))
+    return out, fl.value
+
+
+def point_limit_vjp(uh, ul, gamma, fl, lout):
+    (uh, puh), (ul, pul), (lo, plo) = _p(uh), _p(ul), _p(lout)
+    a, b = np.zeros(8), np.zeros(8)
+    lib().hc_point_limit_vjp(puh, pul, gamma, fl, plo, a.ctypes.data_as(_D), b.ctypes.data_as(_D))
+    return a, b
+
+
+def cell_limiter(x, dt, dx, dy, gamma):
+    """(theta_src, Lambda[4], roots[15], decision bits) for x[88] = A, FsL..FsU,
+    FlL..FlU, S_s, S_llf."""
+    x, px = _p(x)
+    th, lam, rk = ctypes.c_double(0.0), np.zeros(4), np.zeros(15)
+    fl = ctypes.c_uint64(0)
+    lib().hc_cell_limiter(px, dt, dx, dy, gamma, ctypes.byref(th), lam.ctypes.data_as(_D), rk.ctypes.data_as(_D),
+                          ctypes.byref(fl))
+    return th.value, lam, rk, fl.value
+
+
+def cell_limiter_vjp(x, dt, dx, dy, gamma, rk, fl, lth, llam):
+    (x, px), (rk, prk), (llam, pll) = _p(x), _p(rk), _p(llam)
+    out = np.zeros(88)
+    lib().hc_cell_limiter_vjp(px, dt, dx, dy, gamma, prk, fl, lth, pll, out.ctypes.data_as(_D))
+    return out
