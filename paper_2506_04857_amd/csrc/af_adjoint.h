@@ -38,11 +38,13 @@
 #include <stddef.h>
 #include <stdint.h>
 
+// Everything is inlined into the kernels: the reverse kernels make no
+// device-function calls.  (An out-of-line callee was miscompiled: its
+// long-branch expansion used the return-address registers s[30:31] as
+// scratch without saving them, so a wave that took that branch returned
+// into the middle of the callee.)
 #ifndef AF_HD
-#define AF_HD __host__ __device__ inline
-#endif
-#ifndef AF_NOINLINE
-#define AF_NOINLINE __host__ __device__ __attribute__((noinline))
+#define AF_HD __host__ __device__ __forceinline__
 #endif
 
 namespace afadj {
@@ -1086,7 +1088,7 @@ struct CellAdj {
   double Fs[4][NV], Fl[4][NV];
   double Ss[NV], Sllf[NV];
 };
-AF_NOINLINE void cell_limiter_vjp(const CellIn& w, double dt, const AGeo& g, const double* rk, uint64_t fl,
+AF_HD void cell_limiter_vjp(const CellIn& w, double dt, const AGeo& g, const double* rk, uint64_t fl,
                                   double lthsrc, const double* lLam, CellAdj& o) {
   const double gm = g.gamma;
   const double ldx = dt / g.dx, ldy = dt / g.dy;

@@ -619,10 +619,10 @@ AF_HD void source_reverse(const AGeo& g, const Slot q[3][3], const double* lS) {
 }
 
 // Reverse of steps (1)-(2) of a limiter cell whose coefficients depend on
-// the state (out of line: rare).  Scatters the adjoints of A and of the
+// the state (rare).  Scatters the adjoints of A and of the
 // four interfaces' fluxes, and adds those of Ss, Sllf to oSs, oSll.
 template <class Add>
-AF_NOINLINE void limiter_active_vjp(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateM& lk,
+AF_HD void limiter_active_vjp(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateM& lk,
                                     int i, int j, double dt, uint64_t fl, double* oSs, double* oSll) {
   const Ext e = ext_of(g);
   const size_t eid = eidx(e, i, j), en = (size_t)e.ew * e.eh;
@@ -865,11 +865,10 @@ AF_HD void line_reverse(const Slot q[5], double gm, int n, double h, double alph
 }
 
 // Reverse of a point's scaling limiter and first-order LLF state where the
-// limiter acted (out of line: rare, and it would set the register budget of
-// the common path).  Writes the adjoint of U^H to lH and scatters the LLF
+// limiter acted (rare).  Writes the adjoint of U^H to lH and scatters the LLF
 // state's adjoints.
 template <class Add>
-AF_NOINLINE void point_limited_vjp(const AGeo& g, const StateC& u, const Tape& t, const StateM& lk, int kind, int k,
+AF_HD void point_limited_vjp(const AGeo& g, const StateC& u, const Tape& t, const StateM& lk, int kind, int k,
                                    int l, double dt, uint32_t fl, const double* lam, double* lH) {
   PointSt s;
   point_stencil(g, u, t, kind, k, l, s);

@@ -10,7 +10,6 @@ using std::exp;
 using std::fabs;
 using std::sqrt;
 #define AF_HD inline
-#define AF_NOINLINE inline
 #include "af_adjoint_stage.h"
 
 using namespace afadj;
