@@ -216,3 +216,35 @@ def test_adjoint_argument_errors(af):
     with pytest.raises(af.AfMhdError):
         adj.stage(1, u, tape, dt, lam, lam, out)  # lam_out aliases lam_n
     adj.close()
+
+
+def test_adjoint_workload_against_the_cpu_reference_gradient(af):
+    # The adjoint workload at full size (perturbed Alfven wave 256^2, kappa
+    # 1, 400 steps, checkpoints every 20) with the oracle's own dt sequence,
+    # against the FP64 CPU reference: the tangent oracle's directional
+    # derivatives along 8 seeded directions (tests/golden, written by
+    # make_adjoint_reference.py from the oracle alone).  The two trajectories
+    # differ by rounding, and where the wave's div Bbar numerator of phi3 is
+    # at rounding level its sign -- hence the branch of |.| -- can differ
+    # between them; that bounds the agreement (measured ~1e-7), which is far
+    # inside what separates either from central differences (1e-4).
+    import json
+    import os
+
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "adjoint_reference_alfven_perturbed_256.json")
+    ref = json.load(open(path))
+    prob = I.alfven_perturbed(256)
+    n = len(ref["dts"])
+    assert n == I.ADJOINT_STEPS
+    dts = torch.tensor(ref["dts"], dtype=torch.float64, device="cuda")
+    grad, uT = gradient(af, prob, I.sample(prob), n, dts, every=20)
+    J = 0.5 * float(np.sum((uT[0][0] - 1.0) ** 2))
+    say(f"[adjoint] workload J {J:.15e} reference {ref['J']:.15e}")
+    assert abs(J - ref["J"]) <= 1e-10 * ref["J"]
+    for d, (v, want) in enumerate(zip(I.adjoint_directions(prob, len(ref["dJ"])), ref["dJ"])):
+        got = dot(grad, v)
+        e = abs(got - want) / abs(want)
+        say(f"[adjoint] workload direction {d}: GPU adjoint {got:.12e} CPU reference {want:.12e} ({e:.1e})")
+        assert e <= 1e-5
