@@ -43,14 +43,18 @@ BYTES_PER_CELL_POINTS = 256 + 192 * 2.0 / 3.0 + 192
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_points_k_cells_orszag_tang_512_hbm_traffic.txt")
 
 
+# The sources the stage kernels k_points / k_cells are built from (the
+# traffic measurement is theirs; the batch and adjoint sources do not enter).
+STAGE_SOURCES = [os.path.join(ROOT, "paper_2506_04857_amd", "csrc", f)
+                 for f in ("af_stage.hip", "af_device.h", "af_tiles.h")] + [os.path.join(ROOT, "include", "af_mhd.h")]
+
+
 def source_hash() -> str:
-    """SHA-256 over the HIP sources and headers the library is built from."""
+    """SHA-256 over the sources of the stage kernels."""
     h = hashlib.sha256()
-    for d in (os.path.join(ROOT, "paper_2506_04857_amd", "csrc"), os.path.join(ROOT, "include")):
-        for f in sorted(os.listdir(d)):
-            if f.endswith((".hip", ".h")):
-                with open(os.path.join(d, f), "rb") as fh:
-                    h.update(f.encode() + b"\0" + fh.read())
+    for path in STAGE_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 

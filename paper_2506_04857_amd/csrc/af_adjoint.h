@@ -337,23 +337,26 @@ AF_HD double alpha_llf(const double* a, const double* b, double g, int n) {
   const double m2 = dmax(astar(a, b, g, n), astar(b, a, g, n));
   return dmax(m1, m2);
 }
-AF_HD void alpha_llf_vjp(const double* a, const double* b, double g, int n, double l, double* la, double* lb) {
+// The four speeds of the LLF viscosity and which of them is the maximum
+// (0: rho(a), 1: rho(b), 2: alpha*(a,b), 3: alpha*(b,a); ties to the first).
+AF_HD double alpha_llf_arg(const double* a, const double* b, double g, int n, int& arg) {
   const double r1 = srad(a, g, n), r2 = srad(b, g, n);
   const double s1 = astar(a, b, g, n), s2 = astar(b, a, g, n);
   const double m1 = dmax(r1, r2), m2 = dmax(s1, s2);
-  if (m1 < m2) {
-    if (s1 < s2)
-      astar_vjp(b, a, g, n, l, lb, la);
-    else
-      astar_vjp(a, b, g, n, l, la, lb);
-  } else {
-    if (r1 < r2)
-      srad_vjp(b, g, n, l, lb);
-    else
-      srad_vjp(a, g, n, l, la);
-  }
+  arg = m1 < m2 ? (s1 < s2 ? 3 : 2) : (r1 < r2 ? 1 : 0);
+  return dmax(m1, m2);
 }
-
+AF_HD void alpha_llf_vjp_at(const double* a, const double* b, double g, int n, int arg, double l, double* la,
+                            double* lb) {
+  if (arg == 3)
+    astar_vjp(b, a, g, n, l, lb, la);
+  else if (arg == 2)
+    astar_vjp(a, b, g, n, l, la, lb);
+  else if (arg == 1)
+    srad_vjp(b, g, n, l, lb);
+  else
+    srad_vjp(a, g, n, l, la);
+}
 // LLF flux 1/2 [F(a) + F(b) - alpha (b - a)], Section 3.1.
 AF_HD void llf(const double* a, const double* b, double g, int n, double* F) {
   const double al = alpha_llf(a, b, g, n);
@@ -363,7 +366,8 @@ AF_HD void llf(const double* a, const double* b, double g, int n, double* F) {
   for (int c = 0; c < NV; ++c) F[c] = 0.5 * (Fa[c] + Fb[c] - al * (b[c] - a[c]));
 }
 AF_HD void llf_vjp(const double* a, const double* b, double g, int n, const double* lF, double* la, double* lb) {
-  const double al = alpha_llf(a, b, g, n);
+  int arg;
+  const double al = alpha_llf_arg(a, b, g, n, arg);
   double h[NV], lal = 0.0;
   for (int c = 0; c < NV; ++c) {
     h[c] = 0.5 * lF[c];
@@ -373,7 +377,7 @@ AF_HD void llf_vjp(const double* a, const double* b, double g, int n, const doub
   }
   flux_vjp(a, g, n, h, la);
   flux_vjp(b, g, n, h, lb);
-  alpha_llf_vjp(a, b, g, n, lal, la, lb);
+  alpha_llf_vjp_at(a, b, g, n, arg, lal, la, lb);
 }
 
 // ------------------------------------------ point values (Section 2.3)

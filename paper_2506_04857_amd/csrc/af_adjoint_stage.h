@@ -835,10 +835,12 @@ AF_HD void line_scan(const Slot q[5], double gm, int n, double h, double& alpha,
   dB = 0.5 * ((b[0] - 4.0 * b[1] + 3.0 * b[2]) / h + (-3.0 * b[2] + 4.0 * b[3] - b[4]) / h);
 }
 // Passes 2 and 3: the reverse of R = sum_m [sp_m F(w_m) + sd_m alpha w_m]
-// and of dB, one state at a time, then of alpha at its argmax.
+// and of dB, one state at a time, then of alpha at its argmax.  The middle
+// slot is the point itself: its adjoint goes to self (scattered later with
+// the point's other terms) instead of memory.
 template <class Add>
 AF_HD void line_reverse(const Slot q[5], double gm, int n, double h, double alpha, int am, const double* lR,
-                        double ldB) {
+                        double ldB, double* self) {
   const double cp[5] = {1.0, -4.0, 3.0, 0.0, 0.0};
   const double cm[5] = {0.0, 0.0, -3.0, 4.0, -1.0};
   double lal = 0.0;
@@ -853,14 +855,20 @@ AF_HD void line_reverse(const Slot q[5], double gm, int n, double h, double alph
     }
     flux_vjp(w, gm, n, lF, lw);
     lw[4 + n] += sp * ldB;
-    slot_put<Add>(q[m], lw);
+    if (m == 2)
+      for (int c = 0; c < NV; ++c) self[c] += lw[c];
+    else
+      slot_put<Add>(q[m], lw);
   }
   if (am >= 0 && lal != 0.0) {
     double w[NV], lw[NV];
     ld(q[am].src, q[am].L, w);
     zero8(lw);
     srad_vjp(w, gm, n, lal, lw);
-    slot_put<Add>(q[am], lw);
+    if (am == 2)
+      for (int c = 0; c < NV; ++c) self[c] += lw[c];
+    else
+      slot_put<Add>(q[am], lw);
   }
 }
 
@@ -950,11 +958,11 @@ AF_HD void adj_point(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf
       lP[c] = -dt * divB * lH[c];
     }
     psi_vjp(U, lP, lU);
-    put<Add>(kind == 0 ? lk.x : kind == 1 ? lk.y : lk.v, LU, lU);
     double lR[NV];
     for (int c = 0; c < NV; ++c) lR[c] = -dt * lH[c];
-    if (kind != 1) line_reverse<Add>(lx, g.gamma, 0, g.dx, ax, mx, lR, ldiv);
-    if (kind != 0) line_reverse<Add>(ly, g.gamma, 1, g.dy, ay, my, lR, ldiv);
+    if (kind != 1) line_reverse<Add>(lx, g.gamma, 0, g.dx, ax, mx, lR, ldiv, lU);
+    if (kind != 0) line_reverse<Add>(ly, g.gamma, 1, g.dy, ay, my, lR, ldiv, lU);
+    put<Add>(kind == 0 ? lk.x : kind == 1 ? lk.y : lk.v, LU, lU);
     if (kind != 2) {
       // central pair: R = (F(pair1) - F(pair0)) / h in the transverse direction
       const int dir = kind == 0 ? 1 : 0;
