@@ -50,6 +50,10 @@ CASES = [
     ("shock_periodic_newton", lambda: I.stirred(I.random_shock(12, 10, seed=2, bc=I.PERIODIC))),
     ("orszag_tang", lambda: I.orszag_tang(16)),
     ("blast_lowbeta", lambda: I.blast_lowbeta(16)),
+    # dx != dy (a swapped dx / dy anywhere fails) and mixed boundaries
+    ("smooth_mixed_dx_ne_dy", lambda: replace(I.random_smooth(11, 9, seed=7), bc_y=I.OUTFLOW, x1=1.37)),
+    ("shock_mixed_dx_ne_dy", lambda: replace(I.stirred(I.random_shock(14, 12, seed=3, bc=I.OUTFLOW)),
+                                             bc_x=I.PERIODIC, x1=0.8)),
 ]
 
 

@@ -63,6 +63,10 @@ CASES = [
     # phi2 is 0/0 there and its derivative (-1/sqrt(1e-40) = -1e20) turns the
     # summation order of the device atomics into O(1) differences
     ("blast_lowbeta_stirred", lambda: I.stirred(I.blast_lowbeta(32))),
+    # dx != dy and mixed boundaries
+    ("smooth_mixed_dx_ne_dy", lambda: replace(I.random_smooth(23, 18, seed=7), bc_y=I.OUTFLOW, x1=1.37)),
+    ("shock_mixed_dx_ne_dy", lambda: replace(I.stirred(I.random_shock(26, 22, seed=3, bc=I.OUTFLOW)),
+                                             bc_x=I.PERIODIC, x1=0.8)),
 ]
 
 
