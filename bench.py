@@ -108,6 +108,28 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes": n * 8, "launches": 3}))
 
 
+def stream_copy_gbs(af, mib: int = 1024, reps: int = 20) -> dict:
+    """Bandwidth of the library's own stream-copy kernel (read + write bytes
+    per second) on a mib MiB buffer, HIP events on its stream."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        af.stream_copy(src, dst, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        af.stream_copy(src, dst, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    assert bool(torch.equal(src, dst))
+    ms = e0.elapsed_time(e1) / reps
+    return {"gbs": 2 * n * 8 / (ms * 1e-3) / 1e9, "bytes": n * 8, "ms": ms}
+
+
 def timed_steps(ctx, u, steps, stream):
     import torch
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -375,6 +397,7 @@ def main():
     achieved = algo / (us[dom] * 1e-6) / 1e9
     traffic = measured_traffic(args.workload, dom)
 
+    copy = stream_copy_gbs(af)
     out = {
         "metric": METRIC,
         "value": value,
@@ -397,6 +420,9 @@ def main():
         "kernels_us": us,
         "graph_step_value": graph_value,
         "stage_hbm_gbs": BYTES_PER_CELL_STAGE * cells / t_stage / 1e9,
+        "stream_copy": {"gbs": copy["gbs"], "buffer_bytes": copy["bytes"],
+                        "dominant_kernel_frac": achieved / copy["gbs"],
+                        "stage_frac": BYTES_PER_CELL_STAGE * cells / t_stage / 1e9 / copy["gbs"]},
         "admissible": bool(st["admissible"]),
         "fp32_bulk": {"value": value32, "unit": UNIT, "speedup_vs_fp64": value32 / value,
                       "ms_per_step": ms32 / args.steps, "kernels_us": us32,

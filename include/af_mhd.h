@@ -161,6 +161,12 @@ int af_mhd_kernel_times(af_mhd_ctx* c, af_mhd_kernel_times_t* out, int reset);
 
 void af_mhd_destroy(af_mhd_ctx* c);
 
+/* A plain device-to-device copy of n doubles (src, dst 16-byte aligned, n
+ * even), enqueued on hip_stream: the project's own stream-copy kernel, the
+ * attainable-bandwidth reference the stage kernels are compared with.  Not a
+ * step of the method: a measurement aid.  AF_EINVAL on bad pointers or odd n. */
+int af_mhd_stream_copy(const double* src, double* dst, size_t n, void* hip_stream);
+
 /* ------------------------------------------------------------ batches
  * A batch advances n independent grids together (each with its own
  * parameters: sizes, domain, gamma, cfl, kappa, boundaries; the flags must

@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.af_mhd_batch_last_error.restype = ctypes.c_char_p
     L.af_mhd_destroy.argtypes = [vp]
     L.af_mhd_destroy.restype = None
+    L.af_mhd_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.af_mhd_stream_copy.restype = ctypes.c_int
     L.af_mhd_adj_tape_bytes.argtypes = [P]
     L.af_mhd_adj_tape_bytes.restype = ctypes.c_size_t
     L.af_mhd_adj_workspace_bytes.argtypes = [P]
@@ -511,6 +513,20 @@ def evolve(prob, u0, nsteps: int, every: int | None = None, dts=None):
             return lam0
 
     return _Evolve.apply(*u0)
+
+
+def stream_copy(src, dst, stream=None):
+    """dst <- src with the library's stream-copy kernel (contiguous float64
+    device tensors of the same even length), enqueued on stream."""
+    import torch
+
+    if src.dtype != torch.float64 or dst.dtype != torch.float64 or src.numel() != dst.numel():
+        raise ValueError("stream_copy: float64 tensors of equal size")
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    rc = _lib.af_mhd_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(),
+                                 ctypes.c_void_p(s.cuda_stream))
+    if rc != AF_OK:
+        raise AfMhdError(rc, "af_mhd_stream_copy failed")
 
 
 def to_device(state, device="cuda"):

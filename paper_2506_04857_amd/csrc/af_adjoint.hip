@@ -6,8 +6,9 @@
 // cell, update cell); launches run in dependency order on the context's
 // stream.  The reverse sweep scatters with hardware FP64 atomics into the
 // adjoint states and into the intermediate adjoint buffers of the
-// workspace, so its sums are order-dependent at the rounding level (not
-// bitwise reproducible run to run).
+// workspace (the centre's adjoint is gathered by the points instead), so
+// its sums are order-dependent at the rounding level (not bitwise
+// reproducible run to run).
 // No contraction of a*b+c into fused multiply-adds in this translation unit
 // (it must precede the includes to cover the entity functions): the
 // recording forward and the reverse sweep then round like the FP64 oracle,
@@ -138,6 +139,11 @@ __global__ __launch_bounds__(ABLK) void ka_centre(AGeo g, StateC u, Tape t, AdjB
   const long q = gtid();
   if (q >= (long)g.nx * g.ny) return;
   adj_centre<DevAdd>(g, u, t, ab, lk, (int)(q % g.nx), (int)(q / g.nx));
+}
+__global__ __launch_bounds__(ABLK) void ka_centre_gather(AGeo g, AdjBuf ab, StateM lk) {
+  int kind, k, l;
+  if (!point_of(g, gtid(), kind, k, l)) return;
+  adj_centre_gather(g, ab, lk, kind, k, l);
 }
 
 thread_local std::string adj_init_err;
@@ -290,6 +296,7 @@ int af_mhd_adj_stage(af_mhd_adj* c, int k, const af_mhd_state* uk, const void* t
   ka_points<<<nblk((long)g.nxp * g.ny + (long)g.nx * g.nyp + (long)g.nxp * g.nyp), ABLK, 0, s>>>(
       g, u, t, c->ab, lo, ln, lk, dt_dev, a, b);
   ka_centre<<<nblk((long)g.nx * g.ny), ABLK, 0, s>>>(g, u, t, c->ab, lk);
+  ka_centre_gather<<<nblk((long)g.nxp * g.ny + (long)g.nx * g.nyp + (long)g.nxp * g.nyp), ABLK, 0, s>>>(g, c->ab, lk);
   return check_hip(c, "af_mhd_adj_stage");
 }
 

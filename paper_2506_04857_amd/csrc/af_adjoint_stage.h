@@ -981,8 +981,10 @@ AF_HD void adj_point(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf
   }
 }
 
-// Centre of real cell (i, j): the adjoint of the limited centre back to the
-// nine DoFs it is made of.
+// Centre of real cell (i, j), first pass: the adjoint of the limited
+// centre back to A (added here; the last kernel of the sweep, so this
+// thread is the only writer of A(i,j)'s adjoint) and to the raw
+// reconstruction C~, whose adjoint replaces lC(i,j) in place for the gather.
 template <class Add>
 AF_HD void adj_centre(const AGeo& g, const StateC& u, const Tape& t, const AdjBuf& ab, const StateM& lk, int i, int j) {
   const size_t id = (size_t)j * g.nx + i, n = (size_t)g.nx * g.ny;
@@ -991,31 +993,66 @@ AF_HD void adj_centre(const AGeo& g, const StateC& u, const Tape& t, const AdjBu
   bool any = false;
   for (int c = 0; c < NV; ++c) any = any || lC[c] != 0.0;
   if (!any) return;
-  double in[9][NV], Uc[NV], lA[NV], lUc[NV];
-  centre_inputs(g, u, i, j, in);
-  const double* p[9] = {in[0], in[1], in[2], in[3], in[4], in[5], in[6], in[7], in[8]};
-  centre_raw(p, Uc);
+  double lA[NV], lUc[NV];
   zero8(lA);
   zero8(lUc);
-  if (t.cfl[id] & (BL_T1 | BL_T2 | BL_SHIFT | BL_ZERO))
+  if (t.cfl[id] & (BL_T1 | BL_T2 | BL_SHIFT | BL_ZERO)) {
+    double in[9][NV], Uc[NV];
+    centre_inputs(g, u, i, j, in);
+    const double* p[9] = {in[0], in[1], in[2], in[3], in[4], in[5], in[6], in[7], in[8]};
+    centre_raw(p, Uc);
     centre_limit_vjp(in[0], Uc, g.gamma, t.cfl[id], lC, lA, lUc);
-  else
+  } else {
     for (int c = 0; c < NV; ++c) lUc[c] = lC[c];  // C = C~
-  double lf[NV], lv[NV];
-  for (int c = 0; c < NV; ++c) {
-    lA[c] += 36.0 / 16.0 * lUc[c];
-    lf[c] = -4.0 / 16.0 * lUc[c];
-    lv[c] = -1.0 / 16.0 * lUc[c];
   }
-  put<Add>(lk.a, locA(g, i, j), lA);
-  put<Add>(lk.x, locX(g, i, j), lf);
-  put<Add>(lk.x, locX(g, i + 1, j), lf);
-  put<Add>(lk.y, locY(g, i, j), lf);
-  put<Add>(lk.y, locY(g, i, j + 1), lf);
-  put<Add>(lk.v, locV(g, i, j), lv);
-  put<Add>(lk.v, locV(g, i + 1, j), lv);
-  put<Add>(lk.v, locV(g, i, j + 1), lv);
-  put<Add>(lk.v, locV(g, i + 1, j + 1), lv);
+  for (int c = 0; c < NV; ++c) lA[c] += 36.0 / 16.0 * lUc[c];
+  st8(ab.lC, id, n, lUc);
+  double* pa = lk.a + id;
+  for (int c = 0; c < NV; ++c) pa[c * n] += lA[c];
+}
+
+// Second pass, one thread per point of kind (0 X, 1 Y, 2 V): gathers the
+// reconstruction adjoints of the cells whose centre contains the point
+// (-4/16 for a face, -1/16 for a vertex).  A real cell's centre reads its
+// points at node indices 0..n (never mirrored), so a point's cells are its
+// real neighbours: i-1 and i along x for a node index i (wrapped when
+// periodic), the cell itself along a cell index.
+AF_HD void adj_centre_gather(const AGeo& g, const AdjBuf& ab, const StateM& lk, int kind, int k, int l) {
+  const size_t n = (size_t)g.nx * g.ny;
+  int ci[2], cj[2], nci = 0, ncj = 0;
+  auto nodes = [](int k_, int nc, int bc, int* out, int& cnt) {
+    cnt = 0;
+    if (bc == 0) {
+      out[cnt++] = k_ % nc;
+      out[cnt++] = (k_ - 1 + nc) % nc;
+    } else {
+      if (k_ < nc) out[cnt++] = k_;
+      if (k_ - 1 >= 0) out[cnt++] = k_ - 1;
+    }
+  };
+  if (kind == 0 || kind == 2)
+    nodes(k, g.nx, g.bcx, ci, nci);
+  else {
+    ci[0] = k;
+    nci = 1;
+  }
+  if (kind == 1 || kind == 2)
+    nodes(l, g.ny, g.bcy, cj, ncj);
+  else {
+    cj[0] = l;
+    ncj = 1;
+  }
+  const double w = kind == 2 ? -1.0 / 16.0 : -4.0 / 16.0;
+  double sum[NV];
+  zero8(sum);
+  for (int a = 0; a < nci; ++a)
+    for (int b = 0; b < ncj; ++b) {
+      const size_t id = (size_t)cj[b] * g.nx + ci[a];
+      for (int c = 0; c < NV; ++c) sum[c] += ab.lC[id + c * n];
+    }
+  const size_t pid = point_id(g, kind, k, l), pn = point_n(g, kind);
+  double* p = kind == 0 ? lk.x : kind == 1 ? lk.y : lk.v;
+  for (int c = 0; c < NV; ++c) p[pid + c * pn] += w * sum[c];
 }
 
 }  // namespace afadj

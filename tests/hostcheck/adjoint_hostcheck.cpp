@@ -107,6 +107,12 @@ void hc_adjoint(const hc_params* p, int k, const double* const* uk, const void* 
     for (int kk = 0; kk < g.nxp; ++kk) adj_point<HostAdd>(g, u, t, ab, lo, ln, lk, 2, kk, l, dt, a, b);
   for (int j = 0; j < g.ny; ++j)
     for (int i = 0; i < g.nx; ++i) adj_centre<HostAdd>(g, u, t, ab, lk, i, j);
+  for (int l = 0; l < g.ny; ++l)
+    for (int kk = 0; kk < g.nxp; ++kk) adj_centre_gather(g, ab, lk, 0, kk, l);
+  for (int l = 0; l < g.nyp; ++l)
+    for (int i = 0; i < g.nx; ++i) adj_centre_gather(g, ab, lk, 1, i, l);
+  for (int l = 0; l < g.nyp; ++l)
+    for (int kk = 0; kk < g.nxp; ++kk) adj_centre_gather(g, ab, lk, 2, kk, l);
 }
 
 }  // extern "C"

@@ -136,3 +136,16 @@ def test_large_grid_one_step(af, oracle):
     say(f"[edge] 2048x1536: {e:.2e}")
     assert st["admissible"]
     assert e <= REL
+
+
+def test_stream_copy_measurement_kernel(af):
+    # the stream-copy kernel the bench compares bandwidth against
+    import torch
+    for n in (2, 1000, 3 * 2 ** 20 + 6):
+        src = torch.arange(n, dtype=torch.float64, device="cuda")
+        dst = torch.zeros_like(src)
+        af.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+    with pytest.raises(af.AfMhdError):
+        af.stream_copy(src[:-1], dst[:-1])  # odd length
