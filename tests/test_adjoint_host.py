@@ -11,7 +11,9 @@ Pins:
     active, the Orszag-Tang vortex (exact zeros in the sensor), the low-beta
     blast;
   * the gradient of J = 1/2 sum (rho(T) - 1)^2 over several steps, against
-    the tangent oracle run with the same dt sequence.
+    the tangent oracle run with the same dt sequence, along seeded
+    directions and, on a 9 x 7 grid, component by component (every basis
+    direction).
 The error of a dot product is scaled by sum |lam_i (J v)_i| (cancellation
 aware); 1e-11 is the bar (measured: below 1e-12)."""
 import os
@@ -24,6 +26,7 @@ import pytest
 from paper_2506_04857_amd import inputs as I
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from basis_sweep import basis_gradient  # noqa: E402
 from hostcheck import hostcheck as hc  # noqa: E402
 
 BAR = 1e-11
@@ -144,3 +147,22 @@ def test_multistep_gradient_matches_tangent_oracle(oracle, name, make, nsteps):
         got = dot(grad, v)
         scale = absdot(grad, v)
         assert abs(got - want) <= BAR * scale, (got, want, scale)
+
+
+def test_full_gradient_by_basis_sweep(oracle):
+    # every component of the gradient (9 x 7 grid with outflow boundaries,
+    # 2016 initial values, sensor on, stirred so that it is differentiable,
+    # 2 steps) against the tangent oracle along each basis direction
+    prob = I.stirred(I.random_smooth(9, 7, seed=12, bc=I.OUTFLOW), eps=0.05)
+    u0 = I.sample(prob)
+    dts, u = [], u0
+    for _ in range(2):
+        u, d = oracle.step(prob, u)
+        dts.append(d)
+    want, uT = basis_gradient(oracle, prob, u0, dts)
+    lam_T = tuple(np.zeros_like(a) for a in u0)
+    lam_T[0][0] = uT[0][0] - 1.0
+    got, _ = host_gradient(prob, u0, dts, lam_T)
+    scale = max(np.max(np.abs(w)) for w in want)
+    err = max(np.max(np.abs(g - w)) for g, w in zip(got, want)) / scale
+    assert err <= 1e-12, err

@@ -10,6 +10,8 @@
     torch.autograd with sqrt(n) checkpointing: against the tangent oracle run
     with the same dt sequence (1e-10) and central differences of the fast
     stage kernels (h = 1e-6);
+  * the whole gradient on a 16^2 grid, component by component, against the
+    tangent oracle along every basis direction;
   * checkpoint segment length does not change the gradient;
   * argument errors.
 The sums of the reverse sweep use device atomics, so repeated runs agree to
@@ -185,6 +187,29 @@ def test_gradient_with_limiters_and_sensor(af, oracle):
         say(f"[adjoint] stirred shock direction {d}: adjoint {got:.12e} tangent oracle {want:.12e} ({e:.1e})")
         assert e <= BAR
 
+
+
+def test_full_gradient_by_basis_sweep(af, oracle):
+    # Every one of the 8712 components of the gradient on a 16^2 stirred
+    # shock with outflow boundaries (sensor on, limiters active), 2 steps,
+    # checkpoints every step, against the tangent oracle along each basis
+    # direction (about a minute of CPU time for the oracle).
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from basis_sweep import basis_gradient
+    prob = I.stirred(I.random_shock(16, 16, seed=4, bc=I.OUTFLOW))
+    u0 = I.sample(prob)
+    n = 2
+    dts = fixed_dt_sequence(af, prob, u0, n)
+    grad, _ = gradient(af, prob, u0, n, dts, every=1)
+    say("[adjoint] basis sweep 16x16 outflow: GPU gradient done")
+    want, _ = basis_gradient(oracle, prob, u0, dts.cpu().numpy()[:n], chunk=1024,
+                             progress=lambda i, m: say(f"[adjoint]   tangent oracle {i}/{m} directions"))
+    scale = max(np.max(np.abs(w)) for w in want)
+    errs = [np.max(np.abs(g - w)) / scale for g, w in zip(grad, want)]
+    say("[adjoint] basis sweep max error / max |grad| A/X/Y/V " + " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) <= BAR
 
 def test_checkpoint_segment_length_does_not_change_the_gradient(af):
     prob = I.alfven_perturbed(16)
