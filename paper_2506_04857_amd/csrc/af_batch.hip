@@ -90,7 +90,7 @@ __device__ __forceinline__ bool item_range(int items, int& first, int& end, int&
 inline int flat_grid(int items) { return NXCD * ((items + NXCD - 1) / NXCD); }
 
 template <class R, bool PERSIST>
-__global__ __launch_bounds__(PNT, IsF32<R>::value ? 2 : 1) void kb_points(const BInst* __restrict__ I, int n,
+__global__ __launch_bounds__(PNT, 2) void kb_points(const BInst* __restrict__ I, int n,
                                                                           int items, double ca, double cb,
                                                                           Counters* cn) {
   __shared__ R s[point_fields<R>()][PB][PB];

@@ -36,7 +36,7 @@ struct WS {                 // workspace pointers
 };
 
 template <class R>
-__global__ __launch_bounds__(PNT, IsF32<R>::value ? 2 : 1) void k_points(Geo g, CState u, CState un, MState out,
+__global__ __launch_bounds__(PNT, 2) void k_points(Geo g, CState u, CState un, MState out,
                                                                          double* __restrict__ centre,
                                                                          const double* dtp, double ca, double cb,
                                                                          Counters* cn, int ntx, int nty) {

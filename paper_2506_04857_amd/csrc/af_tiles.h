@@ -228,14 +228,14 @@ __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[
 __device__ __forceinline__ int clamp_pt(int i, int np) { return i < -1 ? -1 : (i > np ? np : i); }
 
 // LDS layout (fields of PB x PB values of the compute type): states of the
-// tile's V, X, Y and centre values, then directional records.  The FP64
-// stage publishes the records of two line families at once (families b and
-// a, then c and d: 4 barriers; 32 + 4 x 12 = 80 fields, exactly the 160 KB
-// a workgroup may use); the FP32-bulk stage one family at a time.
-constexpr int SV_ = 0, SX_ = 8, SY_ = 16, SC_ = 24, SR0 = 32, SR1 = 32 + RF, SR2 = 32 + 2 * RF, SR3 = 32 + 3 * RF;
-// LDS fields of a point tile: four records (FP64 stage) or two (FP32-bulk)
+// tile's V, X, Y and centre values, then directional records, one line
+// family at a time.  FP32-bulk stage: full records (flux, spectral radius,
+// c_f, v_n, sqrt(rho)) in FP32, 32 + 2 x 12 fields.  FP64 stage: the
+// record (1/rho, p, c_f, sqrt(rho)) from which a neighbour's evaluation is
+// rebuilt, 32 + 2 x 4 fields = 80 KB.  Either way two workgroups per CU.
+constexpr int SV_ = 0, SX_ = 8, SY_ = 16, SC_ = 24, SR0 = 32, SR1 = 32 + RF;
 template <class R>
-constexpr int point_fields() { return IsF32<R>::value ? 32 + 2 * RF : 32 + 4 * RF; }
+constexpr int point_fields() { return IsF32<R>::value ? 32 + 2 * RF : 40; }
 
 template <class R>
 __device__ __forceinline__ void lds8(R (*s)[PB][PB], int base, int ty, int tx, R U[NV]) {
@@ -248,10 +248,12 @@ __device__ __forceinline__ void sts8(R (*s)[PB][PB], int base, int ty, int tx, c
   for (int c = 0; c < NV; ++c) s[base + c][ty][tx] = (R)U[c];
 }
 
-// One tile of the point update.  R = double: the FP64 stage; R = float:
-// the FP32-bulk stage (LDS holds the compute type; a thread's own states are
-// re-read in FP64 from memory for the evaluations and the FP64
-// accumulation).  s: the caller's LDS, point_fields<R>() x PB x PB values of R.
+// One tile of the point update with full directional records in LDS, one
+// line family per barrier pair: the FP32-bulk stage (R = float; LDS holds
+// the compute type, a thread's own states are re-read in FP64 from memory
+// for the evaluations and the FP64 accumulation).  The FP64 stage runs
+// points_tile_lean below.  s: the caller's LDS, point_fields<R>() x PB x PB
+// values of R.
 template <class R>
 __device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un, MState out,
                                             double* __restrict__ centre, double dt, double ca, double cb,
@@ -484,11 +486,194 @@ __device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un,
   }
 }
 
-template <class R>
-__device__ __forceinline__ void points_tile_4(const Geo& g, CState u, CState un, MState out,
-                                            double* __restrict__ centre, double dt, double ca, double cb,
-                                            Counters* cn, int bx, int by, R (*s)[PB][PB]) {
-  constexpr bool F32 = IsF32<R>::value;
+// ------------------------------------- FP64 point tile in 80 KB of LDS
+// Two workgroups per CU: LDS holds the tile's V, X, Y and centre states
+// (32 fields) and, for the one line family in flight, the record
+// (1/rho, p, c_f, sqrt(rho)) of its two point types (8 fields):
+// 40 x PB x PB doubles = 80 KB.  A point's flux, v_n and spectral radius in
+// the family's direction are rebuilt from its state and record with the
+// operations of eval_dir, so they equal a full evaluation bit for bit.  The
+// families run one per barrier pair in the order b, c, a, d, which keeps at
+// most two point accumulators live.
+constexpr int LQ0 = 32, LQ1 = 36;
+
+// (1/rho, p, c_f in direction dir, sqrt(rho)) of a state, as in eval_dir.
+__device__ __forceinline__ void rec_eval(const double U[NV], const Geo& g, int dir, double q[4]) {
+  double ri, v1, v2, v3, b2, p;
+  prim_r<double>(U, g.gm1, ri, v1, v2, v3, b2, p);
+  const double Bn = dir ? U[5] : U[4];
+  const double c2 = g.gamma * p * ri;
+  const double s = c2 + b2 * ri;
+  double disc = s * s - 4.0 * c2 * Bn * Bn * ri;
+  disc = disc > 0.0 ? disc : 0.0;
+  q[0] = ri;
+  q[1] = p;
+  q[2] = sqrt_r(0.5 * (s + sqrt_r(disc)));
+  q[3] = sqrt_r(U[0]);
+}
+
+// The directional evaluation of a state from its record.
+__device__ __forceinline__ void rec_rebuild(const double U[NV], int dir, const double q[4], DirEval& e) {
+  const double ri = q[0];
+  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
+  const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+  flux_from<double>(U, dir, v1, v2, v3, q[1] + 0.5 * b2, e.F);
+  const double vn = dir ? v2 : v1;
+  e.cf = q[2];
+  e.vn = vn;
+  e.sr = fabs(vn) + q[2];
+  e.sq = q[3];
+}
+
+__device__ __forceinline__ void put_q(double (*s)[PB][PB], int base, int ty, int tx, const double q[4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s[base + c][ty][tx] = q[c];
+}
+
+// State (field base sb) and directional evaluation (record base qb) of the
+// tile point (ty, tx).
+__device__ __forceinline__ void lean_pt(double (*s)[PB][PB], int sb, int qb, int ty, int tx, int dir, DirEval& e,
+                                        double U[NV]) {
+  lds8(s, sb, ty, tx, U);
+  double q[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) q[c] = s[qb + c][ty][tx];
+  rec_rebuild(U, dir, q, e);
+}
+
+// Records of the tile's own points of types sa (-> LQ0) and sb (-> LQ1).
+__device__ __forceinline__ void lean_records(double (*s)[PB][PB], const Geo& g, int ty, int tx, int sa, int sb,
+                                             int dir) {
+  double w[NV], q[4];
+  lds8(s, sa, ty, tx, w);
+  rec_eval(w, g, dir, q);
+  put_q(s, LQ0, ty, tx, q);
+  lds8(s, sb, ty, tx, w);
+  rec_eval(w, g, dir, q);
+  put_q(s, LQ1, ty, tx, q);
+}
+
+// An empty asm that takes an accumulator as read and rewritten: its value is
+// formed before this point, so the arithmetic of a family cannot be sunk
+// past the next barrier with the LDS values it reads kept live instead.
+__device__ __forceinline__ void pin8(double v[NV]) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(v[c]));
+}
+__device__ __forceinline__ void pin_acc(PointAcc<double>& P) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(P.h[c]), "+v"(P.l[c]));
+  asm volatile("" : "+v"(P.divh), "+v"(P.divl));
+}
+
+// FVS line in direction dir through the tile point (ty, tx) of the type with
+// state base so and record LQ0; the line's other type (state base sb, record
+// LQ1) sits at -h/2 (point (ym, xm)) and +h/2 (the point itself), the own
+// type's neighbours at -h (ym, xm) and +h (yp, xp).  alpha (the maximum
+// spectral radius over the five) comes first, so that the FVS sums fold
+// into one vector,
+//   Q = F(-h) - 4F(-h/2) + 4F(+h/2) - F(+h)
+//       + alpha (U(-h) - 4U(-h/2) + 6U - 4U(+h/2) + U(+h)),   h-part -= Q/(2h),
+// and the outer neighbours (with their LLF fluxes, which need the point's
+// own evaluation) come before the inner ones.
+__device__ __forceinline__ double lean_srad(double (*s)[PB][PB], int sb, int qb, int mn, int y, int x) {
+  return fabs(s[sb + mn][y][x] * s[qb][y][x]) + s[qb + 2][y][x];
+}
+
+__device__ __forceinline__ void lean_fvs(double (*s)[PB][PB], int dir, int so, int sb, int ty, int tx, int ym, int xm,
+                                         int yp, int xp, double rh, double lam, PointAcc<double>& P) {
+  const int bn = 4 + dir, mn = 1 + dir;
+  double alpha = lean_srad(s, so, LQ0, mn, ty, tx);
+  alpha = fmax(alpha, lean_srad(s, so, LQ0, mn, ym, xm));
+  alpha = fmax(alpha, lean_srad(s, sb, LQ1, mn, ym, xm));
+  alpha = fmax(alpha, lean_srad(s, sb, LQ1, mn, ty, tx));
+  alpha = fmax(alpha, lean_srad(s, so, LQ0, mn, yp, xp));
+  double Q[NV], dB, jl;
+  {
+    DirEval eo, e;
+    double Uo[NV], U[NV];
+    lean_pt(s, so, LQ0, ty, tx, dir, eo, Uo);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Q[c] = 6.0 * alpha * Uo[c];
+    // -h: LLF flux -F^LLF(U, Uo)
+    lean_pt(s, so, LQ0, ym, xm, dir, e, U);
+    double al = alpha_llf(e, eo, U, Uo);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      Q[c] += e.F[c] + alpha * U[c];
+      P.l[c] += lam * (0.5 * (e.F[c] + eo.F[c] - al * (Uo[c] - U[c])));
+    }
+    dB = U[bn];
+    jl = -U[bn];
+    // +h: LLF flux F^LLF(Uo, U)
+    lean_pt(s, so, LQ0, yp, xp, dir, e, U);
+    al = alpha_llf(eo, e, Uo, U);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      Q[c] += alpha * U[c] - e.F[c];
+      P.l[c] -= lam * (0.5 * (eo.F[c] + e.F[c] - al * (U[c] - Uo[c])));
+    }
+    dB -= U[bn];
+    jl += U[bn];
+  }
+  pin8(Q);
+  pin8(P.l);
+  {
+    DirEval e;
+    double U[NV];
+    // -h/2, +h/2
+    lean_pt(s, sb, LQ1, ym, xm, dir, e, U);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Q[c] -= 4.0 * (e.F[c] + alpha * U[c]);
+    dB -= 4.0 * U[bn];
+    lean_pt(s, sb, LQ1, ty, tx, dir, e, U);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Q[c] += 4.0 * (e.F[c] - alpha * U[c]);
+    dB += 4.0 * U[bn];
+  }
+  const double sh = 0.5 * rh;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) P.h[c] -= Q[c] * sh;
+  P.divh += dB * sh;
+  P.divl += jl * sh;
+}
+
+// Central direction across the tile point (ty, tx) of the type with state
+// base so and record LQ1, between the points of type sd (record LQ0) at
+// (ty, tx) (-h/2) and (yp, xp) (+h/2), which are also its LLF neighbours.
+__device__ __forceinline__ void lean_central(double (*s)[PB][PB], int dir, int so, int sd, int ty, int tx, int yp,
+                                             int xp, double rh, double lam, PointAcc<double>& P) {
+  const int bn = 4 + dir;
+  DirEval eo, e;
+  double Uo[NV], U[NV];
+  lean_pt(s, so, LQ1, ty, tx, dir, eo, Uo);
+  lean_pt(s, sd, LQ0, ty, tx, dir, e, U);
+  {
+    const double ad = alpha_llf(e, eo, U, Uo);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      P.h[c] += e.F[c] * rh;
+      P.l[c] += lam * (0.5 * (e.F[c] + eo.F[c] - ad * (Uo[c] - U[c])));
+    }
+    P.divh -= U[bn] * rh;
+    P.divl -= 0.5 * rh * U[bn];
+  }
+  lean_pt(s, sd, LQ0, yp, xp, dir, e, U);
+  {
+    const double au = alpha_llf(eo, e, Uo, U);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      P.h[c] -= e.F[c] * rh;
+      P.l[c] -= lam * (0.5 * (eo.F[c] + e.F[c] - au * (U[c] - Uo[c])));
+    }
+    P.divh += U[bn] * rh;
+    P.divl += 0.5 * rh * U[bn];
+  }
+}
+
+__device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState un, MState out,
+                                                 double* __restrict__ centre, double dt, double ca, double cb,
+                                                 Counters* cn, int bx, int by, double (*s)[PB][PB]) {
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i0 = bx * (PB - 2) - 1, j0 = by * (PB - 2) - 1;
   const int i = clamp_pt(i0 + tx, g.nxp), j = clamp_pt(j0 + ty, g.nyp);
@@ -496,8 +681,7 @@ __device__ __forceinline__ void points_tile_4(const Geo& g, CState u, CState un,
   const bool outV = inner && i0 + tx < g.nxp && j0 + ty < g.nyp;
   const bool outX = inner && i0 + tx < g.nxp && j0 + ty < g.ny;
   const bool outY = inner && i0 + tx < g.nx && j0 + ty < g.nyp;
-  const double lx = dt * g.rdx, ly = dt * g.rdy;
-  const R rdx = (R)g.rdx, rdy = (R)g.rdy, lxr = (R)lx, lyr = (R)ly;
+  const double lx = dt * g.rdx, ly = dt * g.rdy, rdx = g.rdx, rdy = g.rdy;
   const int txl = tx > 0 ? tx - 1 : tx, txr = tx < PB - 1 ? tx + 1 : tx;
   const int tyd = ty > 0 ? ty - 1 : ty, tyu = ty < PB - 1 ? ty + 1 : ty;
 
@@ -512,215 +696,96 @@ __device__ __forceinline__ void points_tile_4(const Geo& g, CState u, CState un,
     sts8(s, SY_, ty, tx, w);
   }
   __syncthreads();
-  // a thread's own FP64 states (V, X, Y; the centre is kept in C64)
-  double C64[NV];
-  auto own = [&](int which, double U[NV]) {
-    if constexpr (F32) {
-      if (which == 0) ldV(g, u.v, i, j, U);
-      else if (which == 1) ldX(g, u.x, i, j, U);
-      else if (which == 2) ldY(g, u.y, i, j, U);
-      else {
-#pragma unroll
-        for (int c = 0; c < NV; ++c) U[c] = C64[c];
-      }
-    } else {
-      lds8(s, which == 0 ? SV_ : which == 1 ? SX_ : which == 2 ? SY_ : SC_, ty, tx, U);
-    }
-  };
-  // 1: centre values in FP64 (the last column/row's are never used); the
-  //    owner also stores its value for the cell kernel's source term
+  // 1: centre values (the last column/row's are never used); the owner also
+  //    stores its value for the cell kernel's source term.  Read after the
+  //    next barrier.
   {
-    double A[NV], Uc[NV], f[NV], w[NV], q[NV];
+    double A[NV], Uc[NV], f[NV], w[NV], q[NV], C[NV];
     ldA(g, u.a, i, j, A);
-    if constexpr (F32) {
-      ldX(g, u.x, i, j, f);
-      ldX(g, u.x, i + 1, j, w);
-      ldY(g, u.y, i, j, Uc);
-      ldY(g, u.y, i, j + 1, q);
-    } else {
-      lds8(s, SX_, ty, tx, f);
-      lds8(s, SX_, ty, txr, w);
-      lds8(s, SY_, ty, tx, Uc);
-      lds8(s, SY_, tyu, tx, q);
-    }
+    lds8(s, SX_, ty, tx, f);
+    lds8(s, SX_, ty, txr, w);
+    lds8(s, SY_, ty, tx, Uc);
+    lds8(s, SY_, tyu, tx, q);
 #pragma unroll
     for (int c = 0; c < NV; ++c) f[c] = -4.0 * ((f[c] + w[c]) + (Uc[c] + q[c]));
-    if constexpr (F32) {
-      ldV(g, u.v, i, j, Uc);
-      ldV(g, u.v, i + 1, j, w);
-    } else {
-      lds8(s, SV_, ty, tx, Uc);
-      lds8(s, SV_, ty, txr, w);
-    }
+    lds8(s, SV_, ty, tx, Uc);
+    lds8(s, SV_, ty, txr, w);
 #pragma unroll
     for (int c = 0; c < NV; ++c) Uc[c] += w[c];
-    if constexpr (F32) {
-      ldV(g, u.v, i, j + 1, q);
-      ldV(g, u.v, i + 1, j + 1, w);
-    } else {
-      lds8(s, SV_, tyu, tx, q);
-      lds8(s, SV_, tyu, txr, w);
-    }
+    lds8(s, SV_, tyu, tx, q);
+    lds8(s, SV_, tyu, txr, w);
 #pragma unroll
     for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
     const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
-    limit_centre(Uc, A, g.gm1, C64, cn, owner);
-    sts8(s, SC_, ty, tx, C64);
+    limit_centre(Uc, A, g.gm1, C, cn, owner);
+    sts8(s, SC_, ty, tx, C);
     if (owner) {
 #pragma unroll
-      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C64[c];
+      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C[c];
     }
   }
-  DirEvalT<R> e0, e1, en;
-  R U0[NV], U1[NV], Un[NV];
-  LineAcc<R> L;
-  // records of families b (SR0: V in y, SR1: X in y) and a (SR2: V in x,
-  // SR3: Y in x)
-  {
-    double w[NV];
-    own(0, w);
-    eval_dir(w, g, 1, e0);
-    put_rec(s, SR0, ty, tx, e0);
-    eval_dir(w, g, 0, e0);
-    put_rec(s, SR2, ty, tx, e0);
-    own(1, w);
-    eval_dir(w, g, 1, e0);
-    put_rec(s, SR1, ty, tx, e0);
-    own(2, w);
-    eval_dir(w, g, 0, e0);
-    put_rec(s, SR3, ty, tx, e0);
-  }
+  PointAcc<double> PV, PX, PY;
+  double w[NV];
+
+  // b: vertical lines through V and X.  V: FVS in y over V(l-1), X(l-1), V,
+  // X(l), V(l+1).  X: central in y between V(k,j) and V(k,j+1).
+  lean_records(s, g, ty, tx, SV_, SX_, 1);
   __syncthreads();
-  PointAcc<R> PA, PX, PY;
-  // V: FVS in y over V(l-1), X(l-1), V, X(l), V(l+1) (family b), then FVS
-  // in x over V(k-1), Y(k-1), V, Y(k), V(k+1) (family a) -> V complete
-  acc_zero(PA);
-  lds8(s, SV_, ty, tx, U0);
-  get_rec(s, SR0, ty, tx, e0);
-  line_begin(L, e0, U0);
-  get_rec(s, SR0, tyd, tx, en);
-  lds8(s, SV_, tyd, tx, Un);
-  line_outer(L, 5, -1, en, Un, e0, U0);
-  get_rec(s, SR1, tyd, tx, en);
-  lds8(s, SX_, tyd, tx, Un);
-  line_inner(L, 5, -1, en, Un);
-  get_rec(s, SR1, ty, tx, en);
-  lds8(s, SX_, ty, tx, Un);
-  line_inner(L, 5, +1, en, Un);
-  get_rec(s, SR0, tyu, tx, en);
-  lds8(s, SV_, tyu, tx, Un);
-  line_outer(L, 5, +1, en, Un, e0, U0);
-  acc_fvs(PA, L, rdy, lyr);
-  get_rec(s, SR2, ty, tx, e0);
-  line_begin(L, e0, U0);
-  get_rec(s, SR2, ty, txl, en);
-  lds8(s, SV_, ty, txl, Un);
-  line_outer(L, 4, -1, en, Un, e0, U0);
-  get_rec(s, SR3, ty, txl, en);
-  lds8(s, SY_, ty, txl, Un);
-  line_inner(L, 4, -1, en, Un);
-  get_rec(s, SR3, ty, tx, en);
-  lds8(s, SY_, ty, tx, Un);
-  line_inner(L, 4, +1, en, Un);
-  get_rec(s, SR2, ty, txr, en);
-  lds8(s, SV_, ty, txr, Un);
-  line_outer(L, 4, +1, en, Un, e0, U0);
-  acc_fvs(PA, L, rdx, lxr);
-  if (outV) {
-    double w[NV];
-    own(0, w);
-    finish(g, dt, w, PA, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
-  }
-  // X: central in y between V(k,j) and V(k,j+1) (family b)
+  acc_zero(PV);
+  lean_fvs(s, 1, SV_, SX_, ty, tx, tyd, tx, tyu, tx, rdy, ly, PV);
   acc_zero(PX);
-  get_rec(s, SR0, ty, tx, e0);
-  lds8(s, SV_, ty, tx, U0);
-  get_rec(s, SR1, ty, tx, e1);
-  lds8(s, SX_, ty, tx, U1);
-  get_rec(s, SR0, tyu, tx, en);
-  lds8(s, SV_, tyu, tx, Un);
-  acc_central(PX, 5, rdy, lyr, e0, U0, e1, U1, en, Un);
-  // Y: central in x between V(i,l) and V(i+1,l) (family a)
-  acc_zero(PY);
-  get_rec(s, SR2, ty, tx, e0);
-  get_rec(s, SR3, ty, tx, e1);
-  lds8(s, SY_, ty, tx, U1);
-  get_rec(s, SR2, ty, txr, en);
-  lds8(s, SV_, ty, txr, Un);
-  acc_central(PY, 4, rdx, lxr, e0, U0, e1, U1, en, Un);
+  lean_central(s, 1, SX_, SV_, ty, tx, tyu, tx, rdy, ly, PX);
+  pin_acc(PV);
+  pin_acc(PX);
   __syncthreads();
-  // records of families c (SR0: X in x, SR1: C in x) and d (SR2: Y in y,
-  // SR3: C in y)
-  {
-    double w[NV];
-    own(1, w);
-    eval_dir(w, g, 0, e0);
-    put_rec(s, SR0, ty, tx, e0);
-    own(2, w);
-    eval_dir(w, g, 1, e0);
-    put_rec(s, SR2, ty, tx, e0);
-    own(3, w);
-    eval_dir(w, g, 0, e0);
-    put_rec(s, SR1, ty, tx, e0);
-    eval_dir(w, g, 1, e0);
-    put_rec(s, SR3, ty, tx, e0);
-  }
+
+  // c: horizontal lines through X and C.  X: FVS in x over X(k-1), C(k-1),
+  // X, C(k), X(k+1) -> X complete.
+  lean_records(s, g, ty, tx, SX_, SC_, 0);
   __syncthreads();
-  // X: FVS in x over X(k-1), C(k-1), X, C(k), X(k+1) -> X complete
-  lds8(s, SX_, ty, tx, U0);
-  get_rec(s, SR0, ty, tx, e0);
-  line_begin(L, e0, U0);
-  get_rec(s, SR1, ty, tx, en);
-  lds8(s, SC_, ty, tx, Un);
-  line_inner(L, 4, +1, en, Un);
-  get_rec(s, SR0, ty, txl, en);
-  lds8(s, SX_, ty, txl, Un);
-  line_outer(L, 4, -1, en, Un, e0, U0);
-  get_rec(s, SR1, ty, txl, en);
-  lds8(s, SC_, ty, txl, Un);
-  line_inner(L, 4, -1, en, Un);
-  get_rec(s, SR0, ty, txr, en);
-  lds8(s, SX_, ty, txr, Un);
-  line_outer(L, 4, +1, en, Un, e0, U0);
-  acc_fvs(PX, L, rdx, lxr);
+  lean_fvs(s, 0, SX_, SC_, ty, tx, ty, txl, ty, txr, rdx, lx, PX);
   if (outX) {
-    double w[NV];
-    own(1, w);
+    lds8(s, SX_, ty, tx, w);
     finish(g, dt, w, PX, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn);
   }
-  // Y: FVS in y over Y(l-1), C(l-1), Y, C(l), Y(l+1) -> Y complete
-  lds8(s, SY_, ty, tx, U1);
-  get_rec(s, SR2, ty, tx, e0);
-  line_begin(L, e0, U1);
-  get_rec(s, SR3, ty, tx, en);
-  lds8(s, SC_, ty, tx, Un);
-  line_inner(L, 5, +1, en, Un);
-  get_rec(s, SR2, tyd, tx, en);
-  lds8(s, SY_, tyd, tx, Un);
-  line_outer(L, 5, -1, en, Un, e0, U1);
-  get_rec(s, SR3, tyd, tx, en);
-  lds8(s, SC_, tyd, tx, Un);
-  line_inner(L, 5, -1, en, Un);
-  get_rec(s, SR2, tyu, tx, en);
-  lds8(s, SY_, tyu, tx, Un);
-  line_outer(L, 5, +1, en, Un, e0, U1);
-  acc_fvs(PY, L, rdy, lyr);
+  pin_acc(PV);
+  __syncthreads();
+
+  // a: horizontal lines through V and Y.  V: FVS in x over V(k-1), Y(k-1),
+  // V, Y(k), V(k+1) -> V complete.  Y: central in x between V(i,l) and
+  // V(i+1,l).
+  lean_records(s, g, ty, tx, SV_, SY_, 0);
+  __syncthreads();
+  lean_fvs(s, 0, SV_, SY_, ty, tx, ty, txl, ty, txr, rdx, lx, PV);
+  if (outV) {
+    lds8(s, SV_, ty, tx, w);
+    finish(g, dt, w, PV, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
+  }
+  acc_zero(PY);
+  lean_central(s, 0, SY_, SV_, ty, tx, ty, txr, rdx, lx, PY);
+  pin_acc(PY);
+  __syncthreads();
+
+  // d: vertical lines through Y and C.  Y: FVS in y over Y(l-1), C(l-1), Y,
+  // C(l), Y(l+1) -> Y complete.
+  lean_records(s, g, ty, tx, SY_, SC_, 1);
+  __syncthreads();
+  lean_fvs(s, 1, SY_, SC_, ty, tx, tyd, tx, tyu, tx, rdy, ly, PY);
   if (outY) {
-    double w[NV];
-    own(2, w);
+    lds8(s, SY_, ty, tx, w);
     finish(g, dt, w, PY, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
   }
 }
 
-// One tile of the point update (see above); the FP64 stage publishes two
-// line families per barrier (4 barriers, 160 KB of LDS), the FP32-bulk
-// stage one family per barrier (8 barriers, 56 KB: two workgroups per CU).
+// One tile of the point update (see above): the FP64 stage in 80 KB of LDS
+// with rebuilt neighbour evaluations, the FP32-bulk stage with FP32 records;
+// one line family per barrier pair, two workgroups per CU.
 template <class R>
 __device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, MState out,
                                             double* __restrict__ centre, double dt, double ca, double cb,
                                             Counters* cn, int bx, int by, R (*s)[PB][PB]) {
   if constexpr (IsF32<R>::value) points_tile_8<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
-  else points_tile_4<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
+  else points_tile_lean(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
 }
 
 // ------------------------------------------------------ fused cell update
