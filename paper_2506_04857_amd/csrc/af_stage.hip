@@ -60,6 +60,8 @@ __global__ __launch_bounds__(CBX0 * CBY0) void k_cells(Geo g, CState u, const do
 __global__ __launch_bounds__(BLK) void k_dt_partial(Geo g, CState u, double* partial) {
   const long n = g.sc + g.sx + g.sy + g.sv;
   double m = 0.0;
+  // four DoFs per trip: their loads are in flight together
+#pragma unroll 4
   for (long t = (long)blockIdx.x * BLK + threadIdx.x; t < n; t += (long)gridDim.x * BLK) {
     const double* base;
     long plane, off;

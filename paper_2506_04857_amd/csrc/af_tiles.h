@@ -556,7 +556,8 @@ __device__ __forceinline__ void lean_records(double (*s)[PB][PB], const Geo& g, 
 // An empty asm that takes an accumulator as read and rewritten: its value is
 // formed before this point, so the arithmetic of a family cannot be sunk
 // past the next barrier with the LDS values it reads kept live instead.
-__device__ __forceinline__ void pin8(double v[NV]) {
+template <class T>
+__device__ __forceinline__ void pin8(T v[NV]) {
 #pragma unroll
   for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(v[c]));
 }
@@ -885,9 +886,9 @@ __device__ void cell_source(const Geo& g, CState u, const double* __restrict__ c
     }
 #pragma unroll
   for (int c = 0; c < NV; ++c) S[c] = R(0);
-  // One sample at a time (a rolled loop): the states of all nine are never
-  // live together.
-#pragma unroll 1
+  // Three samples per trip: their loads are in flight together, while the
+  // states of all nine are never live together.
+#pragma unroll 3
   for (int q = 0; q < 9; ++q) {
     const int a = q % 3, b = q / 3;
     R fq = f[0];
