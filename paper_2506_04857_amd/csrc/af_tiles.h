@@ -46,9 +46,8 @@ __device__ inline double sensor_pressure(const double U[NV], double gamma) {
 //   b  vertical lines through V and X    (V: FVS in y; X: central in y)
 //   c  horizontal lines through X and C  (X: FVS in x)
 //   d  vertical lines through Y and C    (Y: FVS in y)
-// For each family every point is evaluated once (flux, spectral radius,
-// c_f, v_n, sqrt(rho)) and shared through LDS.  FVS in direction n at a
-// point with line neighbours w0..w4 (offsets -h, -h/2, 0, h/2, h):
+// FVS in direction n at a point with line neighbours w0..w4 (offsets -h,
+// -h/2, 0, h/2, h):
 //   R = D+F+ + D-F- = [F0 - 4F1 + 4F3 - F4 + alpha (w0 - 4w1 + 6w2 - 4w3 + w4)] / (2h)
 //   alpha = max spectral radius over the five, div part (B0 - 4B1 + 4B3 - B4)/(2h).
 // Central direction: R = (F(up) - F(dn))/h, div part (B(up) - B(dn))/h.
@@ -76,76 +75,6 @@ __device__ __forceinline__ void get_rec(R (*s)[H][W], int ty, int tx, DirEvalT<R
   e.sq = s[11][ty][tx];
 }
 
-template <class R>
-__device__ __forceinline__ void put_rec(R (*s)[PB][PB], int base, int ty, int tx, const DirEvalT<R>& e) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) s[base + c][ty][tx] = e.F[c];
-  s[base + 8][ty][tx] = e.sr;
-  s[base + 9][ty][tx] = e.cf;
-  s[base + 10][ty][tx] = e.vn;
-  s[base + 11][ty][tx] = e.sq;
-}
-template <class R>
-__device__ __forceinline__ void get_rec(R (*s)[PB][PB], int base, int ty, int tx, DirEvalT<R>& e) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) e.F[c] = s[base + c][ty][tx];
-  e.sr = s[base + 8][ty][tx];
-  e.cf = s[base + 9][ty][tx];
-  e.vn = s[base + 10][ty][tx];
-  e.sq = s[base + 11][ty][tx];
-}
-
-// Incremental FVS along a line (own point e0/U0 at offset 0).  Outer
-// neighbours (offsets -h, +h) are also the LLF neighbours; inner ones
-// (-h/2, +h/2) enter the FVS sums only.  R = (SF + alpha SW)/(2h).
-template <class R>
-struct LineAcc {
-  R SF[NV], SW[NV], G[NV];
-  R alpha, dB, jl;
-};
-
-template <class R>
-__device__ __forceinline__ void line_begin(LineAcc<R>& L, const DirEvalT<R>& e0, const R U0[NV]) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    L.SF[c] = R(0);
-    L.SW[c] = R(6) * U0[c];
-    L.G[c] = R(0);
-  }
-  L.alpha = e0.sr;
-  L.dB = R(0);
-  L.jl = R(0);
-}
-
-// side = -1 for the neighbour at -h (left/below), +1 at +h.
-template <class R>
-__device__ __forceinline__ void line_outer(LineAcc<R>& L, int bn, int side, const DirEvalT<R>& e, const R U[NV],
-                                           const DirEvalT<R>& e0, const R U0[NV]) {
-  L.alpha = fmax(L.alpha, e.sr);
-  const R al = side < 0 ? alpha_llf(e, e0, U, U0) : alpha_llf(e0, e, U0, U);
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    L.SF[c] -= side * e.F[c];
-    L.SW[c] += U[c];
-    // F^LLF(U0, U) for side +1, -F^LLF(U, U0) for side -1
-    L.G[c] += side < 0 ? R(-0.5) * (e.F[c] + e0.F[c] - al * (U0[c] - U[c]))
-                       : R(0.5) * (e0.F[c] + e.F[c] - al * (U[c] - U0[c]));
-  }
-  L.dB -= side * U[bn];
-  L.jl += side * U[bn];
-}
-
-template <class R>
-__device__ __forceinline__ void line_inner(LineAcc<R>& L, int bn, int side, const DirEvalT<R>& e, const R U[NV]) {
-  L.alpha = fmax(L.alpha, e.sr);
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    L.SF[c] += side * R(4) * e.F[c];
-    L.SW[c] -= R(4) * U[c];
-  }
-  L.dB += side * R(4) * U[bn];
-}
-
 // Point accumulators: high-order RHS h = -R_x - R_y with the div part, and
 // the LLF update l = -dt/dx G_x - dt/dy G_y with its div part.
 template <class R>
@@ -153,35 +82,6 @@ struct PointAcc {
   R h[NV], l[NV];
   R divh, divl;
 };
-
-template <class R>
-__device__ __forceinline__ void acc_fvs(PointAcc<R>& P, const LineAcc<R>& L, R rh, R lam) {
-  const R s = R(0.5) * rh;
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    P.h[c] -= (L.SF[c] + L.alpha * L.SW[c]) * s;
-    P.l[c] -= lam * L.G[c];
-  }
-  P.divh += L.dB * s;
-  P.divl += L.jl * s;
-}
-
-// Central direction across a face point: neighbours dn/up at -h/2, +h/2;
-// they are also its LLF neighbours.
-template <class R>
-__device__ __forceinline__ void acc_central(PointAcc<R>& P, int bn, R rh, R lam, const DirEvalT<R>& ed,
-                                            const R dn[NV], const DirEvalT<R>& e0, const R U0[NV],
-                                            const DirEvalT<R>& eu, const R up[NV]) {
-  const R ad = alpha_llf(ed, e0, dn, U0), au = alpha_llf(e0, eu, U0, up);
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    P.h[c] -= (eu.F[c] - ed.F[c]) * rh;
-    const R G = R(0.5) * (e0.F[c] + eu.F[c] - au * (up[c] - U0[c])) - R(0.5) * (ed.F[c] + e0.F[c] - ad * (U0[c] - dn[c]));
-    P.l[c] -= lam * G;
-  }
-  P.divh += (up[bn] - dn[bn]) * rh;
-  P.divl += R(0.5) * rh * (up[bn] - dn[bn]);
-}
 
 template <class R>
 __device__ __forceinline__ void acc_zero(PointAcc<R>& P) {
@@ -228,14 +128,11 @@ __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[
 __device__ __forceinline__ int clamp_pt(int i, int np) { return i < -1 ? -1 : (i > np ? np : i); }
 
 // LDS layout (fields of PB x PB values of the compute type): states of the
-// tile's V, X, Y and centre values, then directional records, one line
-// family at a time.  FP32-bulk stage: full records (flux, spectral radius,
-// c_f, v_n, sqrt(rho)) in FP32, 32 + 2 x 12 fields.  FP64 stage: the
-// record (1/rho, p, c_f, sqrt(rho)) from which a neighbour's evaluation is
-// rebuilt, 32 + 2 x 4 fields = 80 KB.  Either way two workgroups per CU.
-constexpr int SV_ = 0, SX_ = 8, SY_ = 16, SC_ = 24, SR0 = 32, SR1 = 32 + RF;
+// tile's V, X, Y and centre values, then the records of the line family in
+// flight (see points_tile_lean).
+constexpr int SV_ = 0, SX_ = 8, SY_ = 16, SC_ = 24;
 template <class R>
-constexpr int point_fields() { return IsF32<R>::value ? 32 + 2 * RF : 40; }
+constexpr int point_fields() { return 40; }
 
 template <class R>
 __device__ __forceinline__ void lds8(R (*s)[PB][PB], int base, int ty, int tx, R U[NV]) {
@@ -248,16 +145,207 @@ __device__ __forceinline__ void sts8(R (*s)[PB][PB], int base, int ty, int tx, c
   for (int c = 0; c < NV; ++c) s[base + c][ty][tx] = (R)U[c];
 }
 
-// One tile of the point update with full directional records in LDS, one
-// line family per barrier pair: the FP32-bulk stage (R = float; LDS holds
-// the compute type, a thread's own states are re-read in FP64 from memory
-// for the evaluations and the FP64 accumulation).  The FP64 stage runs
-// points_tile_lean below.  s: the caller's LDS, point_fields<R>() x PB x PB
-// values of R.
+// ---------------------------------- point tile with rebuilt evaluations
+// LDS holds the tile's V, X, Y and centre states (32 fields of the compute
+// type R) and, for the one line family in flight, the record
+// (1/rho, p, c_f, sqrt(rho)) of its two point types (8 fields): 40 x PB x PB
+// values, 80 KB for the FP64 stage (two workgroups per CU), 40 KB for the
+// FP32-bulk one.  A point's flux, v_n and spectral radius in the family's
+// direction are rebuilt from its state and record with the operations of
+// eval_dir (for FP64 bit for bit).  The families run one per barrier pair in
+// the order b, c, a, d, which keeps at most two point accumulators live.
+// FP32-bulk: states and records in FP32; a thread's own FP64 states (for the
+// records, whose pressure recovery is FP64, and for the finish) are re-read
+// from memory, its FP64 centre value kept in registers.
+constexpr int LQ0 = 32, LQ1 = 36;
+
+// Flux of a state held in any type S (the FP64 stage: S = R = double, the
+// operations of flux_from).
+template <class R, class S>
+__device__ __forceinline__ void flux_of(const S U[NV], int dir, R v1, R v2, R v3, R pt, R F[NV]) {
+  const R B1 = (R)U[4], B2 = (R)U[5], B3 = (R)U[6];
+  const R vB = v1 * B1 + v2 * B2 + v3 * B3;
+  const R vn = dir ? v2 : v1;
+  const R Bn = dir ? B2 : B1;
+  F[0] = (R)U[0] * vn;
+  F[1] = vn * (R)U[1] - Bn * B1 + (dir ? R(0) : pt);
+  F[2] = vn * (R)U[2] - Bn * B2 + (dir ? pt : R(0));
+  F[3] = vn * (R)U[3] - Bn * B3;
+  F[4] = dir ? (vn * B1 - Bn * v1) : R(0);
+  F[5] = dir ? R(0) : (vn * B2 - Bn * v2);
+  F[6] = vn * B3 - Bn * v3;
+  F[7] = ((R)U[7] + pt) * vn - Bn * vB;
+}
+
+// (1/rho, p, c_f in direction dir, sqrt(rho)) of an FP64 state, as in
+// eval_dir.
 template <class R>
-__device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un, MState out,
-                                            double* __restrict__ centre, double dt, double ca, double cb,
-                                            Counters* cn, int bx, int by, R (*s)[PB][PB]) {
+__device__ __forceinline__ void rec_eval(const double U[NV], const Geo& g, int dir, R q[4]) {
+  R ri, v1, v2, v3, b2, p;
+  prim_r<R>(U, g.gm1, ri, v1, v2, v3, b2, p);
+  const R Bn = dir ? (R)U[5] : (R)U[4];
+  const R c2 = (R)g.gamma * p * ri;
+  const R s = c2 + b2 * ri;
+  R disc = s * s - R(4) * c2 * Bn * Bn * ri;
+  disc = disc > R(0) ? disc : R(0);
+  q[0] = ri;
+  q[1] = p;
+  q[2] = sqrt_r(R(0.5) * (s + sqrt_r(disc)));
+  q[3] = sqrt_r((R)U[0]);
+}
+
+// The directional evaluation of a state from its record.
+template <class R>
+__device__ __forceinline__ void rec_rebuild(const R U[NV], int dir, const R q[4], DirEvalT<R>& e) {
+  const R ri = q[0];
+  const R v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
+  const R b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+  flux_of<R, R>(U, dir, v1, v2, v3, q[1] + R(0.5) * b2, e.F);
+  const R vn = dir ? v2 : v1;
+  e.cf = q[2];
+  e.vn = vn;
+  e.sr = fabs(vn) + q[2];
+  e.sq = q[3];
+}
+
+// State (field base sb) and directional evaluation (record base qb) of the
+// tile point (ty, tx).
+template <class R>
+__device__ __forceinline__ void lean_pt(R (*s)[PB][PB], int sb, int qb, int ty, int tx, int dir, DirEvalT<R>& e,
+                                        R U[NV]) {
+  lds8(s, sb, ty, tx, U);
+  R q[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) q[c] = s[qb + c][ty][tx];
+  rec_rebuild(U, dir, q, e);
+}
+
+// Records of the tile's own points, FP64 states ua (-> LQ0) and ub (-> LQ1).
+template <class R>
+__device__ __forceinline__ void lean_records(R (*s)[PB][PB], const Geo& g, int ty, int tx, const double ua[NV],
+                                             const double ub[NV], int dir) {
+  R q[4];
+  rec_eval(ua, g, dir, q);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s[LQ0 + c][ty][tx] = q[c];
+  rec_eval(ub, g, dir, q);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s[LQ1 + c][ty][tx] = q[c];
+}
+
+// An empty asm that takes an accumulator as read and rewritten: its value is
+// formed before this point, so the arithmetic of a family cannot be sunk
+// past the next barrier with the LDS values it reads kept live instead.
+template <class T>
+__device__ __forceinline__ void pin8(T v[NV]) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(v[c]));
+}
+template <class R>
+__device__ __forceinline__ void pin_acc(PointAcc<R>& P) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(P.h[c]), "+v"(P.l[c]));
+  asm volatile("" : "+v"(P.divh), "+v"(P.divl));
+}
+
+// FVS line in direction dir through the tile point (ty, tx) of the type with
+// state base so and record LQ0; the line's other type (state base sb, record
+// LQ1) sits at -h/2 (point (ym, xm)) and +h/2 (the point itself), the own
+// type's neighbours at -h (ym, xm) and +h (yp, xp).  alpha (the maximum
+// spectral radius over the five) comes first, so that the FVS sums fold
+// into one vector,
+//   Q = F(-h) - 4F(-h/2) + 4F(+h/2) - F(+h)
+//       + alpha (U(-h) - 4U(-h/2) + 6U - 4U(+h/2) + U(+h)),   h-part -= Q/(2h),
+// and the outer neighbours (with their LLF fluxes, which need the point's
+// own evaluation) come before the inner ones.  CENTRAL: the line's +h/2
+// point (the tile point of the other type) also takes its central
+// difference across this line, between this point and the +h neighbour,
+// into P2 (families b and a), from the same evaluations.
+template <class R>
+__device__ __forceinline__ R lean_srad(R (*s)[PB][PB], int sb, int qb, int mn, int y, int x) {
+  return fabs(s[sb + mn][y][x] * s[qb][y][x]) + s[qb + 2][y][x];
+}
+
+template <class R, bool CENTRAL>
+__device__ __forceinline__ void lean_fvs(R (*s)[PB][PB], int dir, int so, int sb, int ty, int tx, int ym, int xm,
+                                         int yp, int xp, R rh, R lam, PointAcc<R>& P, PointAcc<R>& P2) {
+  const int bn = 4 + dir, mn = 1 + dir;
+  R alpha = lean_srad(s, so, LQ0, mn, ty, tx);
+  alpha = fmax(alpha, lean_srad(s, so, LQ0, mn, ym, xm));
+  alpha = fmax(alpha, lean_srad(s, sb, LQ1, mn, ym, xm));
+  alpha = fmax(alpha, lean_srad(s, sb, LQ1, mn, ty, tx));
+  alpha = fmax(alpha, lean_srad(s, so, LQ0, mn, yp, xp));
+  R Q[NV], dB, jl;
+  DirEvalT<R> eo, e;
+  R Uo[NV], U[NV];
+  lean_pt(s, so, LQ0, ty, tx, dir, eo, Uo);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Q[c] = R(6) * alpha * Uo[c];
+  // -h: LLF flux -F^LLF(U, Uo)
+  lean_pt(s, so, LQ0, ym, xm, dir, e, U);
+  R al = alpha_llf(e, eo, U, Uo);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    Q[c] += e.F[c] + alpha * U[c];
+    P.l[c] += lam * (R(0.5) * (e.F[c] + eo.F[c] - al * (Uo[c] - U[c])));
+  }
+  dB = U[bn];
+  jl = -U[bn];
+  // +h: LLF flux F^LLF(Uo, U)
+  lean_pt(s, so, LQ0, yp, xp, dir, e, U);
+  al = alpha_llf(eo, e, Uo, U);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    Q[c] += alpha * U[c] - e.F[c];
+    P.l[c] -= lam * (R(0.5) * (eo.F[c] + e.F[c] - al * (U[c] - Uo[c])));
+  }
+  dB -= U[bn];
+  jl += U[bn];
+  pin8(Q);
+  pin8(P.l);
+  {
+    DirEvalT<R> ei;
+    R Ui[NV];
+    // -h/2, +h/2
+    lean_pt(s, sb, LQ1, ym, xm, dir, ei, Ui);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Q[c] -= R(4) * (ei.F[c] + alpha * Ui[c]);
+    dB -= R(4) * Ui[bn];
+    lean_pt(s, sb, LQ1, ty, tx, dir, ei, Ui);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Q[c] += R(4) * (ei.F[c] - alpha * Ui[c]);
+    dB += R(4) * Ui[bn];
+    if constexpr (CENTRAL) {
+      // the +h/2 point's central direction between this point (-h/2 from
+      // it) and the +h neighbour (+h/2 from it), with their evaluations
+      const R ad = alpha_llf(eo, ei, Uo, Ui), au = alpha_llf(ei, e, Ui, U);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        P2.h[c] += eo.F[c] * rh;
+        P2.l[c] += lam * (R(0.5) * (eo.F[c] + ei.F[c] - ad * (Ui[c] - Uo[c])));
+      }
+      P2.divh -= Uo[bn] * rh;
+      P2.divl -= R(0.5) * rh * Uo[bn];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        P2.h[c] -= e.F[c] * rh;
+        P2.l[c] -= lam * (R(0.5) * (ei.F[c] + e.F[c] - au * (U[c] - Ui[c])));
+      }
+      P2.divh += U[bn] * rh;
+      P2.divl += R(0.5) * rh * U[bn];
+    }
+  }
+  const R sh = R(0.5) * rh;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) P.h[c] -= Q[c] * sh;
+  P.divh += dB * sh;
+  P.divl += jl * sh;
+}
+
+template <class R>
+__device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState un, MState out,
+                                                 double* __restrict__ centre, double dt, double ca, double cb,
+                                                 Counters* cn, int bx, int by, R (*s)[PB][PB]) {
   constexpr bool F32 = IsF32<R>::value;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i0 = bx * (PB - 2) - 1, j0 = by * (PB - 2) - 1;
@@ -270,6 +358,17 @@ __device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un,
   const R rdx = (R)g.rdx, rdy = (R)g.rdy, lxr = (R)lx, lyr = (R)ly;
   const int txl = tx > 0 ? tx - 1 : tx, txr = tx < PB - 1 ? tx + 1 : tx;
   const int tyd = ty > 0 ? ty - 1 : ty, tyu = ty < PB - 1 ? ty + 1 : ty;
+  // a thread's own FP64 state of type 0 V, 1 X, 2 Y (LDS for the FP64
+  // stage, memory for the FP32-bulk one)
+  auto own = [&](int which, double U[NV]) {
+    if constexpr (F32) {
+      if (which == 0) ldV(g, u.v, i, j, U);
+      else if (which == 1) ldX(g, u.x, i, j, U);
+      else ldY(g, u.y, i, j, U);
+    } else {
+      lds8(s, which == 0 ? SV_ : which == 1 ? SX_ : SY_, ty, tx, U);
+    }
+  };
 
   // 0: the tile's raw point values into LDS
   {
@@ -282,29 +381,10 @@ __device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un,
     sts8(s, SY_, ty, tx, w);
   }
   __syncthreads();
-  // a thread's own FP64 states (V, X, Y from memory; for the FP32-bulk
-  // stage the FP64 centre values wait in LDS of their own)
-  double C64[NV];
-  double (*c64)[PB][PB] = nullptr;
-  if constexpr (F32) {
-    __shared__ double c64_lds[NV][PB][PB];
-    c64 = c64_lds;
-  }
-  auto own = [&](int which, double U[NV]) {
-    if constexpr (F32) {
-      if (which == 0) ldV(g, u.v, i, j, U);
-      else if (which == 1) ldX(g, u.x, i, j, U);
-      else if (which == 2) ldY(g, u.y, i, j, U);
-      else {
-#pragma unroll
-        for (int c = 0; c < NV; ++c) U[c] = c64[c][ty][tx];
-      }
-    } else {
-      lds8(s, which == 0 ? SV_ : which == 1 ? SX_ : which == 2 ? SY_ : SC_, ty, tx, U);
-    }
-  };
   // 1: centre values in FP64 (the last column/row's are never used); the
-  //    owner also stores its value for the cell kernel's source term
+  //    owner also stores its value for the cell kernel's source term.  Read
+  //    after the next barrier.
+  double C[NV];
   {
     double A[NV], Uc[NV], f[NV], w[NV], q[NV];
     ldA(g, u.a, i, j, A);
@@ -340,384 +420,6 @@ __device__ __forceinline__ void points_tile_8(const Geo& g, CState u, CState un,
 #pragma unroll
     for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
     const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
-    limit_centre(Uc, A, g.gm1, C64, cn, owner);
-    sts8(s, SC_, ty, tx, C64);
-    if constexpr (F32) {
-#pragma unroll
-      for (int c = 0; c < NV; ++c) c64[c][ty][tx] = C64[c];
-    }
-    if (owner) {
-#pragma unroll
-      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C64[c];
-    }
-  }
-  PointAcc<R> PA, PB_;
-  DirEvalT<R> e0, e1, en;
-  R U0[NV], U1[NV], Un[NV];
-  LineAcc<R> L;
-
-  // b: vertical lines through V and X.  V: FVS in y over V(l-1), X(l-1), V,
-  // X(l), V(l+1).  X: central in y between V(k,j) and V(k,j+1).
-  {
-    double w[NV];
-    own(0, w);
-    eval_dir(w, g, 1, e0);
-    own(1, w);
-    eval_dir(w, g, 1, e1);
-  }
-  lds8(s, SV_, ty, tx, U0);
-  lds8(s, SX_, ty, tx, U1);
-  put_rec(s, SR0, ty, tx, e0);
-  put_rec(s, SR1, ty, tx, e1);
-  __syncthreads();
-  acc_zero(PA);  // V
-  acc_zero(PB_); // X
-  line_begin(L, e0, U0);
-  get_rec(s, SR0, tyd, tx, en);
-  lds8(s, SV_, tyd, tx, Un);
-  line_outer(L, 5, -1, en, Un, e0, U0);
-  get_rec(s, SR1, tyd, tx, en);
-  lds8(s, SX_, tyd, tx, Un);
-  line_inner(L, 5, -1, en, Un);
-  line_inner(L, 5, +1, e1, U1);
-  get_rec(s, SR0, tyu, tx, en);
-  lds8(s, SV_, tyu, tx, Un);
-  line_outer(L, 5, +1, en, Un, e0, U0);
-  acc_fvs(PA, L, rdy, lyr);
-  acc_central(PB_, 5, rdy, lyr, e0, U0, e1, U1, en, Un);
-  __syncthreads();
-
-  // a: horizontal lines through V and Y.  V: FVS in x over V(k-1), Y(k-1),
-  // V, Y(k), V(k+1) -> V complete.  Y: central in x between V(i,l), V(i+1,l).
-  {
-    double w[NV];
-    own(0, w);
-    eval_dir(w, g, 0, e0);
-    own(2, w);
-    eval_dir(w, g, 0, e1);
-  }
-  lds8(s, SY_, ty, tx, U1);
-  put_rec(s, SR0, ty, tx, e0);
-  put_rec(s, SR1, ty, tx, e1);
-  __syncthreads();
-  line_begin(L, e0, U0);
-  get_rec(s, SR0, ty, txl, en);
-  lds8(s, SV_, ty, txl, Un);
-  line_outer(L, 4, -1, en, Un, e0, U0);
-  get_rec(s, SR1, ty, txl, en);
-  lds8(s, SY_, ty, txl, Un);
-  line_inner(L, 4, -1, en, Un);
-  line_inner(L, 4, +1, e1, U1);
-  get_rec(s, SR0, ty, txr, en);
-  lds8(s, SV_, ty, txr, Un);
-  line_outer(L, 4, +1, en, Un, e0, U0);
-  acc_fvs(PA, L, rdx, lxr);
-  if (outV) {
-    double w[NV];
-    own(0, w);
-    finish(g, dt, w, PA, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
-  }
-  acc_zero(PA);  // now Y
-  acc_central(PA, 4, rdx, lxr, e0, U0, e1, U1, en, Un);
-  __syncthreads();
-
-  // c: horizontal lines through X and C.  X: FVS in x over X(k-1), C(k-1),
-  // X, C(k), X(k+1) -> X complete.
-  {
-    double w[NV];
-    own(1, w);
-    eval_dir(w, g, 0, e0);
-    own(3, w);
-    eval_dir(w, g, 0, e1);
-  }
-  lds8(s, SX_, ty, tx, U0);
-  lds8(s, SC_, ty, tx, Un);
-  put_rec(s, SR0, ty, tx, e0);
-  put_rec(s, SR1, ty, tx, e1);
-  __syncthreads();
-  line_begin(L, e0, U0);
-  line_inner(L, 4, +1, e1, Un);
-  get_rec(s, SR0, ty, txl, en);
-  lds8(s, SX_, ty, txl, Un);
-  line_outer(L, 4, -1, en, Un, e0, U0);
-  get_rec(s, SR1, ty, txl, en);
-  lds8(s, SC_, ty, txl, Un);
-  line_inner(L, 4, -1, en, Un);
-  get_rec(s, SR0, ty, txr, en);
-  lds8(s, SX_, ty, txr, Un);
-  line_outer(L, 4, +1, en, Un, e0, U0);
-  acc_fvs(PB_, L, rdx, lxr);
-  if (outX) {
-    double w[NV];
-    own(1, w);
-    finish(g, dt, w, PB_, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn);
-  }
-  __syncthreads();
-
-  // d: vertical lines through Y and C.  Y: FVS in y over Y(l-1), C(l-1), Y,
-  // C(l), Y(l+1) -> Y complete.
-  {
-    double w[NV];
-    own(2, w);
-    eval_dir(w, g, 1, e0);
-    own(3, w);
-    eval_dir(w, g, 1, e1);
-  }
-  lds8(s, SC_, ty, tx, Un);
-  put_rec(s, SR0, ty, tx, e0);
-  put_rec(s, SR1, ty, tx, e1);
-  __syncthreads();
-  line_begin(L, e0, U1);
-  line_inner(L, 5, +1, e1, Un);
-  get_rec(s, SR0, tyd, tx, en);
-  lds8(s, SY_, tyd, tx, Un);
-  line_outer(L, 5, -1, en, Un, e0, U1);
-  get_rec(s, SR1, tyd, tx, en);
-  lds8(s, SC_, tyd, tx, Un);
-  line_inner(L, 5, -1, en, Un);
-  get_rec(s, SR0, tyu, tx, en);
-  lds8(s, SY_, tyu, tx, Un);
-  line_outer(L, 5, +1, en, Un, e0, U1);
-  acc_fvs(PA, L, rdy, lyr);
-  if (outY) {
-    double w[NV];
-    own(2, w);
-    finish(g, dt, w, PA, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
-  }
-}
-
-// ------------------------------------- FP64 point tile in 80 KB of LDS
-// Two workgroups per CU: LDS holds the tile's V, X, Y and centre states
-// (32 fields) and, for the one line family in flight, the record
-// (1/rho, p, c_f, sqrt(rho)) of its two point types (8 fields):
-// 40 x PB x PB doubles = 80 KB.  A point's flux, v_n and spectral radius in
-// the family's direction are rebuilt from its state and record with the
-// operations of eval_dir, so they equal a full evaluation bit for bit.  The
-// families run one per barrier pair in the order b, c, a, d, which keeps at
-// most two point accumulators live.
-constexpr int LQ0 = 32, LQ1 = 36;
-
-// (1/rho, p, c_f in direction dir, sqrt(rho)) of a state, as in eval_dir.
-__device__ __forceinline__ void rec_eval(const double U[NV], const Geo& g, int dir, double q[4]) {
-  double ri, v1, v2, v3, b2, p;
-  prim_r<double>(U, g.gm1, ri, v1, v2, v3, b2, p);
-  const double Bn = dir ? U[5] : U[4];
-  const double c2 = g.gamma * p * ri;
-  const double s = c2 + b2 * ri;
-  double disc = s * s - 4.0 * c2 * Bn * Bn * ri;
-  disc = disc > 0.0 ? disc : 0.0;
-  q[0] = ri;
-  q[1] = p;
-  q[2] = sqrt_r(0.5 * (s + sqrt_r(disc)));
-  q[3] = sqrt_r(U[0]);
-}
-
-// The directional evaluation of a state from its record.
-__device__ __forceinline__ void rec_rebuild(const double U[NV], int dir, const double q[4], DirEval& e) {
-  const double ri = q[0];
-  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
-  const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
-  flux_from<double>(U, dir, v1, v2, v3, q[1] + 0.5 * b2, e.F);
-  const double vn = dir ? v2 : v1;
-  e.cf = q[2];
-  e.vn = vn;
-  e.sr = fabs(vn) + q[2];
-  e.sq = q[3];
-}
-
-__device__ __forceinline__ void put_q(double (*s)[PB][PB], int base, int ty, int tx, const double q[4]) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) s[base + c][ty][tx] = q[c];
-}
-
-// State (field base sb) and directional evaluation (record base qb) of the
-// tile point (ty, tx).
-__device__ __forceinline__ void lean_pt(double (*s)[PB][PB], int sb, int qb, int ty, int tx, int dir, DirEval& e,
-                                        double U[NV]) {
-  lds8(s, sb, ty, tx, U);
-  double q[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) q[c] = s[qb + c][ty][tx];
-  rec_rebuild(U, dir, q, e);
-}
-
-// Records of the tile's own points of types sa (-> LQ0) and sb (-> LQ1).
-__device__ __forceinline__ void lean_records(double (*s)[PB][PB], const Geo& g, int ty, int tx, int sa, int sb,
-                                             int dir) {
-  double w[NV], q[4];
-  lds8(s, sa, ty, tx, w);
-  rec_eval(w, g, dir, q);
-  put_q(s, LQ0, ty, tx, q);
-  lds8(s, sb, ty, tx, w);
-  rec_eval(w, g, dir, q);
-  put_q(s, LQ1, ty, tx, q);
-}
-
-// An empty asm that takes an accumulator as read and rewritten: its value is
-// formed before this point, so the arithmetic of a family cannot be sunk
-// past the next barrier with the LDS values it reads kept live instead.
-template <class T>
-__device__ __forceinline__ void pin8(T v[NV]) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(v[c]));
-}
-__device__ __forceinline__ void pin_acc(PointAcc<double>& P) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(P.h[c]), "+v"(P.l[c]));
-  asm volatile("" : "+v"(P.divh), "+v"(P.divl));
-}
-
-// FVS line in direction dir through the tile point (ty, tx) of the type with
-// state base so and record LQ0; the line's other type (state base sb, record
-// LQ1) sits at -h/2 (point (ym, xm)) and +h/2 (the point itself), the own
-// type's neighbours at -h (ym, xm) and +h (yp, xp).  alpha (the maximum
-// spectral radius over the five) comes first, so that the FVS sums fold
-// into one vector,
-//   Q = F(-h) - 4F(-h/2) + 4F(+h/2) - F(+h)
-//       + alpha (U(-h) - 4U(-h/2) + 6U - 4U(+h/2) + U(+h)),   h-part -= Q/(2h),
-// and the outer neighbours (with their LLF fluxes, which need the point's
-// own evaluation) come before the inner ones.
-__device__ __forceinline__ double lean_srad(double (*s)[PB][PB], int sb, int qb, int mn, int y, int x) {
-  return fabs(s[sb + mn][y][x] * s[qb][y][x]) + s[qb + 2][y][x];
-}
-
-__device__ __forceinline__ void lean_fvs(double (*s)[PB][PB], int dir, int so, int sb, int ty, int tx, int ym, int xm,
-                                         int yp, int xp, double rh, double lam, PointAcc<double>& P) {
-  const int bn = 4 + dir, mn = 1 + dir;
-  double alpha = lean_srad(s, so, LQ0, mn, ty, tx);
-  alpha = fmax(alpha, lean_srad(s, so, LQ0, mn, ym, xm));
-  alpha = fmax(alpha, lean_srad(s, sb, LQ1, mn, ym, xm));
-  alpha = fmax(alpha, lean_srad(s, sb, LQ1, mn, ty, tx));
-  alpha = fmax(alpha, lean_srad(s, so, LQ0, mn, yp, xp));
-  double Q[NV], dB, jl;
-  {
-    DirEval eo, e;
-    double Uo[NV], U[NV];
-    lean_pt(s, so, LQ0, ty, tx, dir, eo, Uo);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) Q[c] = 6.0 * alpha * Uo[c];
-    // -h: LLF flux -F^LLF(U, Uo)
-    lean_pt(s, so, LQ0, ym, xm, dir, e, U);
-    double al = alpha_llf(e, eo, U, Uo);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      Q[c] += e.F[c] + alpha * U[c];
-      P.l[c] += lam * (0.5 * (e.F[c] + eo.F[c] - al * (Uo[c] - U[c])));
-    }
-    dB = U[bn];
-    jl = -U[bn];
-    // +h: LLF flux F^LLF(Uo, U)
-    lean_pt(s, so, LQ0, yp, xp, dir, e, U);
-    al = alpha_llf(eo, e, Uo, U);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      Q[c] += alpha * U[c] - e.F[c];
-      P.l[c] -= lam * (0.5 * (eo.F[c] + e.F[c] - al * (U[c] - Uo[c])));
-    }
-    dB -= U[bn];
-    jl += U[bn];
-  }
-  pin8(Q);
-  pin8(P.l);
-  {
-    DirEval e;
-    double U[NV];
-    // -h/2, +h/2
-    lean_pt(s, sb, LQ1, ym, xm, dir, e, U);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) Q[c] -= 4.0 * (e.F[c] + alpha * U[c]);
-    dB -= 4.0 * U[bn];
-    lean_pt(s, sb, LQ1, ty, tx, dir, e, U);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) Q[c] += 4.0 * (e.F[c] - alpha * U[c]);
-    dB += 4.0 * U[bn];
-  }
-  const double sh = 0.5 * rh;
-#pragma unroll
-  for (int c = 0; c < NV; ++c) P.h[c] -= Q[c] * sh;
-  P.divh += dB * sh;
-  P.divl += jl * sh;
-}
-
-// Central direction across the tile point (ty, tx) of the type with state
-// base so and record LQ1, between the points of type sd (record LQ0) at
-// (ty, tx) (-h/2) and (yp, xp) (+h/2), which are also its LLF neighbours.
-__device__ __forceinline__ void lean_central(double (*s)[PB][PB], int dir, int so, int sd, int ty, int tx, int yp,
-                                             int xp, double rh, double lam, PointAcc<double>& P) {
-  const int bn = 4 + dir;
-  DirEval eo, e;
-  double Uo[NV], U[NV];
-  lean_pt(s, so, LQ1, ty, tx, dir, eo, Uo);
-  lean_pt(s, sd, LQ0, ty, tx, dir, e, U);
-  {
-    const double ad = alpha_llf(e, eo, U, Uo);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      P.h[c] += e.F[c] * rh;
-      P.l[c] += lam * (0.5 * (e.F[c] + eo.F[c] - ad * (Uo[c] - U[c])));
-    }
-    P.divh -= U[bn] * rh;
-    P.divl -= 0.5 * rh * U[bn];
-  }
-  lean_pt(s, sd, LQ0, yp, xp, dir, e, U);
-  {
-    const double au = alpha_llf(eo, e, Uo, U);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      P.h[c] -= e.F[c] * rh;
-      P.l[c] -= lam * (0.5 * (eo.F[c] + e.F[c] - au * (U[c] - Uo[c])));
-    }
-    P.divh += U[bn] * rh;
-    P.divl += 0.5 * rh * U[bn];
-  }
-}
-
-__device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState un, MState out,
-                                                 double* __restrict__ centre, double dt, double ca, double cb,
-                                                 Counters* cn, int bx, int by, double (*s)[PB][PB]) {
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int i0 = bx * (PB - 2) - 1, j0 = by * (PB - 2) - 1;
-  const int i = clamp_pt(i0 + tx, g.nxp), j = clamp_pt(j0 + ty, g.nyp);
-  const bool inner = tx >= 1 && tx < PB - 1 && ty >= 1 && ty < PB - 1;
-  const bool outV = inner && i0 + tx < g.nxp && j0 + ty < g.nyp;
-  const bool outX = inner && i0 + tx < g.nxp && j0 + ty < g.ny;
-  const bool outY = inner && i0 + tx < g.nx && j0 + ty < g.nyp;
-  const double lx = dt * g.rdx, ly = dt * g.rdy, rdx = g.rdx, rdy = g.rdy;
-  const int txl = tx > 0 ? tx - 1 : tx, txr = tx < PB - 1 ? tx + 1 : tx;
-  const int tyd = ty > 0 ? ty - 1 : ty, tyu = ty < PB - 1 ? ty + 1 : ty;
-
-  // 0: the tile's raw point values into LDS
-  {
-    double w[NV];
-    ldV(g, u.v, i, j, w);
-    sts8(s, SV_, ty, tx, w);
-    ldX(g, u.x, i, j, w);
-    sts8(s, SX_, ty, tx, w);
-    ldY(g, u.y, i, j, w);
-    sts8(s, SY_, ty, tx, w);
-  }
-  __syncthreads();
-  // 1: centre values (the last column/row's are never used); the owner also
-  //    stores its value for the cell kernel's source term.  Read after the
-  //    next barrier.
-  {
-    double A[NV], Uc[NV], f[NV], w[NV], q[NV], C[NV];
-    ldA(g, u.a, i, j, A);
-    lds8(s, SX_, ty, tx, f);
-    lds8(s, SX_, ty, txr, w);
-    lds8(s, SY_, ty, tx, Uc);
-    lds8(s, SY_, tyu, tx, q);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) f[c] = -4.0 * ((f[c] + w[c]) + (Uc[c] + q[c]));
-    lds8(s, SV_, ty, tx, Uc);
-    lds8(s, SV_, ty, txr, w);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) Uc[c] += w[c];
-    lds8(s, SV_, tyu, tx, q);
-    lds8(s, SV_, tyu, txr, w);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
-    const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
     limit_centre(Uc, A, g.gm1, C, cn, owner);
     sts8(s, SC_, ty, tx, C);
     if (owner) {
@@ -725,28 +427,39 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
       for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C[c];
     }
   }
-  PointAcc<double> PV, PX, PY;
-  double w[NV];
+  auto own_c = [&](double U[NV]) {
+    if constexpr (F32) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) U[c] = C[c];
+    } else {
+      lds8(s, SC_, ty, tx, U);
+    }
+  };
+  PointAcc<R> PV, PX, PY;
+  double w[NV], w2[NV];
 
   // b: vertical lines through V and X.  V: FVS in y over V(l-1), X(l-1), V,
   // X(l), V(l+1).  X: central in y between V(k,j) and V(k,j+1).
-  lean_records(s, g, ty, tx, SV_, SX_, 1);
+  own(0, w);
+  own(1, w2);
+  lean_records(s, g, ty, tx, w, w2, 1);
   __syncthreads();
   acc_zero(PV);
-  lean_fvs(s, 1, SV_, SX_, ty, tx, tyd, tx, tyu, tx, rdy, ly, PV);
   acc_zero(PX);
-  lean_central(s, 1, SX_, SV_, ty, tx, tyu, tx, rdy, ly, PX);
+  lean_fvs<R, true>(s, 1, SV_, SX_, ty, tx, tyd, tx, tyu, tx, rdy, lyr, PV, PX);
   pin_acc(PV);
   pin_acc(PX);
   __syncthreads();
 
   // c: horizontal lines through X and C.  X: FVS in x over X(k-1), C(k-1),
   // X, C(k), X(k+1) -> X complete.
-  lean_records(s, g, ty, tx, SX_, SC_, 0);
+  own(1, w);
+  own_c(w2);
+  lean_records(s, g, ty, tx, w, w2, 0);
   __syncthreads();
-  lean_fvs(s, 0, SX_, SC_, ty, tx, ty, txl, ty, txr, rdx, lx, PX);
+  lean_fvs<R, false>(s, 0, SX_, SC_, ty, tx, ty, txl, ty, txr, rdx, lxr, PX, PX);
   if (outX) {
-    lds8(s, SX_, ty, tx, w);
+    own(1, w);
     finish(g, dt, w, PX, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn);
   }
   pin_acc(PV);
@@ -755,38 +468,39 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
   // a: horizontal lines through V and Y.  V: FVS in x over V(k-1), Y(k-1),
   // V, Y(k), V(k+1) -> V complete.  Y: central in x between V(i,l) and
   // V(i+1,l).
-  lean_records(s, g, ty, tx, SV_, SY_, 0);
+  own(0, w);
+  own(2, w2);
+  lean_records(s, g, ty, tx, w, w2, 0);
   __syncthreads();
-  lean_fvs(s, 0, SV_, SY_, ty, tx, ty, txl, ty, txr, rdx, lx, PV);
+  acc_zero(PY);
+  lean_fvs<R, true>(s, 0, SV_, SY_, ty, tx, ty, txl, ty, txr, rdx, lxr, PV, PY);
+  pin_acc(PY);
   if (outV) {
-    lds8(s, SV_, ty, tx, w);
+    own(0, w);
     finish(g, dt, w, PV, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
   }
-  acc_zero(PY);
-  lean_central(s, 0, SY_, SV_, ty, tx, ty, txr, rdx, lx, PY);
-  pin_acc(PY);
   __syncthreads();
 
   // d: vertical lines through Y and C.  Y: FVS in y over Y(l-1), C(l-1), Y,
   // C(l), Y(l+1) -> Y complete.
-  lean_records(s, g, ty, tx, SY_, SC_, 1);
+  own(2, w);
+  own_c(w2);
+  lean_records(s, g, ty, tx, w, w2, 1);
   __syncthreads();
-  lean_fvs(s, 1, SY_, SC_, ty, tx, tyd, tx, tyu, tx, rdy, ly, PY);
+  lean_fvs<R, false>(s, 1, SY_, SC_, ty, tx, tyd, tx, tyu, tx, rdy, lyr, PY, PY);
   if (outY) {
-    lds8(s, SY_, ty, tx, w);
+    own(2, w);
     finish(g, dt, w, PY, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
   }
 }
 
-// One tile of the point update (see above): the FP64 stage in 80 KB of LDS
-// with rebuilt neighbour evaluations, the FP32-bulk stage with FP32 records;
-// one line family per barrier pair, two workgroups per CU.
+// One tile of the point update (see above): FP64 stage (R = double) or
+// FP32-bulk stage (R = float).
 template <class R>
 __device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, MState out,
                                             double* __restrict__ centre, double dt, double ca, double cb,
                                             Counters* cn, int bx, int by, R (*s)[PB][PB]) {
-  if constexpr (IsF32<R>::value) points_tile_8<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
-  else points_tile_lean(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
+  points_tile_lean<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
 }
 
 // ------------------------------------------------------ fused cell update
