@@ -358,20 +358,28 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
   const R rdx = (R)g.rdx, rdy = (R)g.rdy, lxr = (R)lx, lyr = (R)ly;
   const int txl = tx > 0 ? tx - 1 : tx, txr = tx < PB - 1 ? tx + 1 : tx;
   const int tyd = ty > 0 ? ty - 1 : ty, tyu = ty < PB - 1 ? ty + 1 : ty;
-  // a thread's own FP64 state of type 0 V, 1 X, 2 Y (LDS for the FP64
-  // stage, memory for the FP32-bulk one)
+  // a thread's own FP64 states of type 0 V, 1 X, 2 Y: from LDS for the
+  // FP64 stage; kept in registers from the tile load for the FP32-bulk one
+  // (whose LDS holds FP32)
+  double oV[F32 ? NV : 1], oX[F32 ? NV : 1], oY[F32 ? NV : 1];
   auto own = [&](int which, double U[NV]) {
     if constexpr (F32) {
-      if (which == 0) ldV(g, u.v, i, j, U);
-      else if (which == 1) ldX(g, u.x, i, j, U);
-      else ldY(g, u.y, i, j, U);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) U[c] = which == 0 ? oV[c] : which == 1 ? oX[c] : oY[c];
     } else {
       lds8(s, which == 0 ? SV_ : which == 1 ? SX_ : SY_, ty, tx, U);
     }
   };
 
   // 0: the tile's raw point values into LDS
-  {
+  if constexpr (F32) {
+    ldV(g, u.v, i, j, oV);
+    sts8(s, SV_, ty, tx, oV);
+    ldX(g, u.x, i, j, oX);
+    sts8(s, SX_, ty, tx, oX);
+    ldY(g, u.y, i, j, oY);
+    sts8(s, SY_, ty, tx, oY);
+  } else {
     double w[NV];
     ldV(g, u.v, i, j, w);
     sts8(s, SV_, ty, tx, w);
@@ -389,9 +397,11 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
     double A[NV], Uc[NV], f[NV], w[NV], q[NV];
     ldA(g, u.a, i, j, A);
     if constexpr (F32) {
-      ldX(g, u.x, i, j, f);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) f[c] = oX[c];
       ldX(g, u.x, i + 1, j, w);
-      ldY(g, u.y, i, j, Uc);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) Uc[c] = oY[c];
       ldY(g, u.y, i, j + 1, q);
     } else {
       lds8(s, SX_, ty, tx, f);
@@ -402,7 +412,8 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
 #pragma unroll
     for (int c = 0; c < NV; ++c) f[c] = -4.0 * ((f[c] + w[c]) + (Uc[c] + q[c]));
     if constexpr (F32) {
-      ldV(g, u.v, i, j, Uc);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) Uc[c] = oV[c];
       ldV(g, u.v, i + 1, j, w);
     } else {
       lds8(s, SV_, ty, tx, Uc);

@@ -6,10 +6,16 @@ against a plain copy kernel of known size.
   python -m paper_2506_04857_amd.rocprof_summary kernels STATS_CSV
   python -m paper_2506_04857_amd.rocprof_summary traffic \\
       --fetch FETCH_CSV --write WRITE_CSV --copy-fetch CSV --copy-write CSV --copy-bytes N
+  python -m paper_2506_04857_amd.rocprof_summary sq --insts CSV --busy CSV [--cus 256 --xcc 8]
 
 FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; the copy kernel reads
 and writes N bytes per dispatch, so each counter's scale factor is
 (N / 1024) / (its reading on the copy kernel).
+
+sq: per-wave instruction counts (SQ_INSTS_* / SQ_WAVES, from the --insts
+pass) and busy fractions as rocprof's VALUBusy, 100 * SQ_ACTIVE_INST_* /
+CUs / (GRBM_GUI_ACTIVE / XCCs) (from the --busy pass), each the mean over
+the kernel's dispatches.
 """
 from __future__ import annotations
 
@@ -75,7 +81,33 @@ def main(argv=None):
     for f in ("fetch", "write", "copy-fetch", "copy-write"):
         b.add_argument("--" + f, required=True)
     b.add_argument("--copy-bytes", type=float, required=True)
+    c = sub.add_parser("sq")
+    c.add_argument("--insts", required=True)
+    c.add_argument("--busy", required=True)
+    c.add_argument("--cus", type=int, default=256)
+    c.add_argument("--xcc", type=int, default=8)
     args = ap.parse_args(argv)
+    if args.cmd == "sq":
+        get = lambda path, name: counter_per_dispatch(path, name)
+        waves = get(args.insts, "SQ_WAVES")
+        ins = {n: get(args.insts, "SQ_INSTS_" + n) for n in
+               ("VALU", "VALU_FMA_F64", "VALU_ADD_F64", "VALU_MUL_F64", "VALU_TRANS_F64", "LDS", "SALU")}
+        grbm = get(args.busy, "GRBM_GUI_ACTIVE")
+        av = get(args.busy, "SQ_ACTIVE_INST_VALU")
+        al = get(args.busy, "SQ_ACTIVE_INST_LDS")
+        conf = get(args.busy, "SQ_LDS_BANK_CONFLICT")
+        print(f"{'kernel':<20} {'waves':>6} {'VALU':>6} {'FMA64':>6} {'ADD64':>6} {'MUL64':>6} {'TRANS64':>7} "
+              f"{'LDS':>5} {'SALU':>5} {'VALU%':>7} {'LDS%':>6} {'LDSconfl':>9}")
+        for k in sorted(waves):
+            if not (k.startswith("k_points") or k.startswith("k_cells")) or k not in grbm:
+                continue
+            w = waves[k]
+            per = {n: ins[n].get(k, 0.0) / w for n in ins}
+            cyc = args.cus * grbm[k] / args.xcc
+            print(f"{k:<20} {w:>6.0f} {per['VALU']:>6.0f} {per['VALU_FMA_F64']:>6.0f} {per['VALU_ADD_F64']:>6.0f} "
+                  f"{per['VALU_MUL_F64']:>6.0f} {per['VALU_TRANS_F64']:>7.0f} {per['LDS']:>5.0f} {per['SALU']:>5.0f} "
+                  f"{100 * av.get(k, 0.0) / cyc:>6.1f}% {100 * al.get(k, 0.0) / cyc:>5.1f}% {conf.get(k, 0.0):>9.3g}")
+        return
     if args.cmd == "kernels":
         print(f"{'kernel':<34} {'calls':>6} {'avg us':>10} {'min us':>10} {'max us':>10} {'share %':>8}")
         for k in kernel_stats(args.stats_csv):
