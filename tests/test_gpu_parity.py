@@ -120,6 +120,9 @@ def gpu_run(af, prob, u0, nsteps, t_final=None):
 @pytest.mark.parametrize("name,make,nsteps", [
     ("alfven_32_100steps", lambda: I.alfven(32), 100),
     ("orszag_tang_128_kappa0_100steps", lambda: replace(I.orszag_tang(128), kappa=0.0), 100),
+    # the benchmark's size (sensor off: with it on, the method's own
+    # sensitivity is the bar, see the next test)
+    ("orszag_tang_512_kappa0_100steps", lambda: replace(I.orszag_tang(512), kappa=0.0), 100),
     ("smooth_24x19_outflow_kappa0_60steps", lambda: replace(I.random_smooth(24, 19, seed=9, bc=I.OUTFLOW),
                                                             kappa=0.0), 60),
 ])
