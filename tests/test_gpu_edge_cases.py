@@ -1,7 +1,8 @@
 """Edge cases of the HIP stage through the C ABI: exact properties the
 scheme has (constant states, mass conservation), degenerate physics
-(B = 0), extreme aspect ratios, the smallest grids and a large grid, each
-against the FP64 oracle where one is computed."""
+(B = 0), extreme aspect ratios, the smallest grids, a large grid, and
+plane sets past 2^31 bytes (translation invariance of a tiled periodic
+state), each against the FP64 oracle where one is computed."""
 import sys
 from dataclasses import replace
 
@@ -137,6 +138,50 @@ def test_large_grid_one_step(af, oracle):
     assert st["admissible"]
     assert e <= REL
 
+
+
+def test_arrays_past_2gib_translation_invariance(af):
+    # 16384 x 4096 cells: every [8][ny][nx] plane set is 4.3 GB, past 2^31
+    # bytes, so any 32-bit byte offset would wrap.  The Orszag-Tang 512^2
+    # data tiled 32 x 8 times is periodic with period 512 (and the domain
+    # grows by powers of two, so dx and dy are the same numbers), hence one
+    # stage of it must reproduce the 512^2 stage in every block, bit for bit.
+    import torch
+    small = I.orszag_tang(512)
+    rx, ry = 32, 8
+    big = replace(small, nx=512 * rx, ny=512 * ry, x1=small.x0 + rx * (small.x1 - small.x0),
+                  y1=small.y0 + ry * (small.y1 - small.y0))
+    assert big.dx == small.dx and big.dy == small.dy
+    u0 = I.sample(small)
+    dt = 1.0e-3
+    ref = []
+    ctx = af.Context(small)
+    du = af.to_device(u0)
+    out = af.empty_state(small)
+    ctx.dt_dev.fill_(dt)
+    ctx.af_mhd_stage(0, du, du, out)
+    torch.cuda.synchronize()
+    ref = af.to_host(out)
+    ctx.close()
+    del du, out
+    say(f"[edge] {big.nx}x{big.ny}: {8 * big.nx * big.ny * 8 / 2**30:.1f} GiB per plane set")
+    ctx = af.Context(big)
+    dbig = tuple(torch.from_numpy(np.tile(a, (1, ry, rx))).to("cuda") for a in u0)
+    out = af.empty_state(big)
+    ctx.dt_dev.fill_(dt)
+    ctx.af_mhd_stage(0, dbig, dbig, out)
+    torch.cuda.synchronize()
+    st = ctx.af_mhd_stats(out)
+    del dbig
+    worst = 0.0
+    for q in range(4):
+        got = out[q].cpu().numpy().reshape(8, ry, 512, rx, 512)
+        worst = max(worst, float(np.max(np.abs(got - ref[q][:, None, :, None, :]))))
+        del got
+    ctx.close()
+    say(f"[edge] tiled stage vs 512^2 stage: max |difference| {worst:.3e}")
+    assert st["admissible"]
+    assert worst == 0.0
 
 def test_stream_copy_measurement_kernel(af):
     # the stream-copy kernel the bench compares bandwidth against
