@@ -54,26 +54,7 @@ __device__ inline double sensor_pressure(const double U[NV], double gamma) {
 // The first-order LLF state uses the four neighbours of the point (the
 // line neighbours at +-h for FVS directions, at +-h/2 for the central one).
 constexpr int PB = 16, PNT = PB * PB;
-constexpr int RF = 12;  // record: F[8], sr, cf, vn, sq
-
-template <int W, int H, class R>
-__device__ __forceinline__ void put_rec(R (*s)[H][W], int ty, int tx, const DirEvalT<R>& e) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) s[c][ty][tx] = e.F[c];
-  s[8][ty][tx] = e.sr;
-  s[9][ty][tx] = e.cf;
-  s[10][ty][tx] = e.vn;
-  s[11][ty][tx] = e.sq;
-}
-template <int W, int H, class R>
-__device__ __forceinline__ void get_rec(R (*s)[H][W], int ty, int tx, DirEvalT<R>& e) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) e.F[c] = s[c][ty][tx];
-  e.sr = s[8][ty][tx];
-  e.cf = s[9][ty][tx];
-  e.vn = s[10][ty][tx];
-  e.sq = s[11][ty][tx];
-}
+constexpr int RF = 12;  // exchange fields of the cell tile: record (4) + LLF flux (8)
 
 // Point accumulators: high-order RHS h = -R_x - R_y with the div part, and
 // the LLF update l = -dt/dx G_x - dt/dy G_y with its div part.
@@ -201,6 +182,21 @@ __device__ __forceinline__ void rec_rebuild(const R U[NV], int dir, const R q[4]
   const R v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
   const R b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
   flux_of<R, R>(U, dir, v1, v2, v3, q[1] + R(0.5) * b2, e.F);
+  const R vn = dir ? v2 : v1;
+  e.cf = q[2];
+  e.vn = vn;
+  e.sr = fabs(vn) + q[2];
+  e.sq = q[3];
+}
+
+// The directional evaluation of an FP64 state from its record, with the
+// operations of eval_dir for either compute type (|B|^2 summed in FP64).
+template <class R>
+__device__ __forceinline__ void rec_rebuild_d(const double U[NV], int dir, const R q[4], DirEvalT<R>& e) {
+  const R ri = q[0];
+  const R v1 = (R)U[1] * ri, v2 = (R)U[2] * ri, v3 = (R)U[3] * ri;
+  const R b2 = (R)(U[4] * U[4] + U[5] * U[5] + U[6] * U[6]);
+  flux_of<R, double>(U, dir, v1, v2, v3, q[1] + R(0.5) * b2, e.F);
   const R vn = dir ? v2 : v1;
   e.cf = q[2];
   e.vn = vn;
@@ -680,7 +676,7 @@ template <class R, int CBX, int CBY>
 struct CellsLDS {
   R dfx[NV][CBY][CBX];  // theta^s (F_simpson - F^LLF) at the x-interface left of each cell
   R dfy[NV][CBY][CBX];  // ... at the y-interface below it; they give H_L, H_R, H_D, H_U
-  R x[RF][CBY][CBX];    // exchange: primitives, records, F^LLF (and Lambda, FP64 stage)
+  R x[RF][CBY][CBX];    // exchange: primitives; records (0-3) and F^LLF (4-11); Lambda (FP64 stage)
   R ts[2][CBY][CBX];    // theta^s at the two interfaces
   R phi[CBY + 1][CBX + 1][4];
   double lam[IsF32<R>::value ? 4 : 1][CBY][CBX];
@@ -756,8 +752,11 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   for (int c = 0; c < NV; ++c) G[c] = A[c];
 
   // 3: interfaces.  dir 0: the x-interface left of the cell, dir 1: the
-  //    y-interface below it.  The cell's own directional evaluation is
-  //    shared with the neighbour on the other side through LDS.
+  //    y-interface below it.  The cell's record (1/rho, p, c_f, sqrt(rho))
+  //    goes through LDS (fields 0-3 of the exchange buffer); the neighbour
+  //    on the other side rebuilds the cell's directional evaluation from it
+  //    and the average it loads anyway.  The interface's LLF flux goes to
+  //    fields 4-11 for the cell on its other side.
   const R kappa = (R)g.kappa;
 #pragma unroll
   for (int dir = 0; dir < 2; ++dir) {
@@ -765,13 +764,18 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
     {
       DirEvalT<R> eA, eN;
       double AN[NV];
-      eval_dir(A, g, dir, eA);
-      put_rec(s_x, ty, tx, eA);
+      R q[4];
+      rec_eval(A, g, dir, q);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s_x[c][ty][tx] = q[c];
+      rec_rebuild_d(A, dir, q, eA);
       __syncthreads();
       const int nx_ = dir == 0 ? tx - 1 : tx, ny_ = dir == 0 ? ty : ty - 1;
       if (dir == 0) ldA(g, u.a, i - 1, j, AN); else ldA(g, u.a, i, j - 1, AN);
       if ((dir == 0 ? tx : ty) > 0) {
-        get_rec(s_x, ny_, nx_, eN);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q[c] = s_x[c][ny_][nx_];
+        rec_rebuild_d(AN, dir, q, eN);
       } else {
         eval_dir(AN, g, dir, eN);
       }
@@ -790,16 +794,18 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
       interface_flux(g, dir, w0, w1, w2, eN, AN, eA, A, ts, Fl, dF);
       s_ts[dir][ty][tx] = ts;
 #pragma unroll
-      for (int c = 0; c < NV; ++c) (dir == 0 ? s_dfx : s_dfy)[c][ty][tx] = dF[c];
+      for (int c = 0; c < NV; ++c) {
+        (dir == 0 ? s_dfx : s_dfy)[c][ty][tx] = dF[c];
+        s_x[4 + c][ty][tx] = Fl[c];
+      }
     }
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NV; ++c) s_x[c][ty][tx] = Fl[c];
-    __syncthreads();
+    // the records of this direction are read and the fluxes published; the
+    // next direction's records and fluxes are written after its own barrier
     const double lam = dir == 0 ? lx : ly;
 #pragma unroll
-    for (int c = 0; c < NV; ++c) G[c] += lam * (double)(Fl[c] - (dir == 0 ? s_x[c][ty][txr] : s_x[c][tyu][tx]));
-    __syncthreads();
+    for (int c = 0; c < NV; ++c)
+      G[c] += lam * (double)(Fl[c] - (dir == 0 ? s_x[4 + c][ty][txr] : s_x[4 + c][tyu][tx]));
   }
   // H_I(c): anti-diffusive updates of the four interfaces
   auto H = [&](int I, int c) -> double {
