@@ -712,14 +712,23 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   constexpr int PW = CBX + 3, PH = CBY + 3;
   static_assert(5 * PW * PH <= RF * CBX * CBY, "primitives must fit the exchange buffer");
   R* prim = &s_x[0][0][0];
-  for (int it = tid; it < PW * PH; it += CNT) {
-    const int a = it % PW, b = it / PW;
-    double U[NV];
+  {
+    // one or two items per thread, the loads of both issued first
+    static_assert(CNT < PW * PH && PW * PH <= 2 * CNT, "one or two primitive items per thread");
+    const int it2 = tid + CNT;
+    const bool two = it2 < PW * PH;
+    double U[NV], U2[NV];
     R q[5];
-    ldA(g, u.a, clamp_prim(i0 - 2 + a, g.nx), clamp_prim(j0 - 2 + b, g.ny), U);
+    ldA(g, u.a, clamp_prim(i0 - 2 + tid % PW, g.nx), clamp_prim(j0 - 2 + tid / PW, g.ny), U);
+    if (two) ldA(g, u.a, clamp_prim(i0 - 2 + it2 % PW, g.nx), clamp_prim(j0 - 2 + it2 / PW, g.ny), U2);
     sensor_prims(U, g.gamma, q);
 #pragma unroll
-    for (int m = 0; m < 5; ++m) prim[m * PW * PH + it] = q[m];
+    for (int m = 0; m < 5; ++m) prim[m * PW * PH + tid] = q[m];
+    if (two) {
+      sensor_prims(U2, g.gamma, q);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) prim[m * PW * PH + it2] = q[m];
+    }
   }
   __syncthreads();
   // 1b: indicators on [i0-1, i0+CBX) x [j0-1, j0+CBY)
