@@ -136,8 +136,8 @@ __device__ __forceinline__ void sts8(R (*s)[PB][PB], int base, int ty, int tx, c
 // eval_dir (for FP64 bit for bit).  The families run one per barrier pair in
 // the order b, c, a, d, which keeps at most two point accumulators live.
 // FP32-bulk: states and records in FP32; a thread's own FP64 states (for the
-// records, whose pressure recovery is FP64, and for the finish) are re-read
-// from memory, its FP64 centre value kept in registers.
+// records, whose pressure recovery is FP64, and for the finish) and its FP64
+// centre value stay in registers from the tile load.
 constexpr int LQ0 = 32, LQ1 = 36;
 
 // Flux of a state held in any type S (the FP64 stage: S = R = double, the
