@@ -11,8 +11,9 @@
 //   k_cells   cell averages (Sections 2.2, 3.1-3.4): Simpson and LLF fluxes,
 //             shock sensor, nine-point and LLF Powell sources, parametrized
 //             flux limiter, limited update in flux form, SSP combination
-// Both are LDS-tiled: every derived quantity a tile needs is computed once
-// per tile and shared through LDS; there are no HBM intermediates.
+// Both are LDS-tiled: a tile's states and the costly per-point quantities
+// are computed once and shared through LDS, cheap ones (fluxes) rebuilt
+// where they are used; only the centre values pass through HBM.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
