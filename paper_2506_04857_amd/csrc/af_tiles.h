@@ -754,6 +754,15 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   double A[NV], G[NV];
   R S[NV];
   ldA(g, u.a, i, j, A);
+  // div B of the LLF source (phase 4) from the neighbours' B1, B2: for the
+  // FP64 stage from the sensor primitives still in LDS (they hold B exactly;
+  // phase 3 overwrites them), for the FP32-bulk stage from memory in phase 4
+  double divb = 0.0;
+  if constexpr (!IsF32<R>::value) {
+    const int pc = (ty + 2) * PW + (tx + 2);
+    divb = (prim[3 * PW * PH + pc + 1] - prim[3 * PW * PH + pc - 1]) * (0.5 * g.rdx);
+    divb += (prim[4 * PW * PH + pc + PW] - prim[4 * PW * PH + pc - PW]) * (0.5 * g.rdy);
+  }
   // 2: nine-point source (before the interfaces: its temporaries and theirs
   //    are never live together)
   cell_source(g, u, centre, i, j, S);
@@ -832,15 +841,17 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   double Allf[NV], Asrc[NV];
   {
     R P[NV];
-    double AN[NV], b;
-    ldA(g, u.a, i + 1, j, AN);
-    b = AN[4];
-    ldA(g, u.a, i - 1, j, AN);
-    double divb = (b - AN[4]) * (0.5 * g.rdx);
-    ldA(g, u.a, i, j + 1, AN);
-    b = AN[5];
-    ldA(g, u.a, i, j - 1, AN);
-    divb += (b - AN[5]) * (0.5 * g.rdy);
+    if constexpr (IsF32<R>::value) {
+      double AN[NV], b;
+      ldA(g, u.a, i + 1, j, AN);
+      b = AN[4];
+      ldA(g, u.a, i - 1, j, AN);
+      divb = (b - AN[4]) * (0.5 * g.rdx);
+      ldA(g, u.a, i, j + 1, AN);
+      b = AN[5];
+      ldA(g, u.a, i, j - 1, AN);
+      divb += (b - AN[5]) * (0.5 * g.rdy);
+    }
     psi(A, P);
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
