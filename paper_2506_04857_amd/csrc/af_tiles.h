@@ -776,6 +776,8 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   //    and the average it loads anyway.  The interface's LLF flux goes to
   //    fields 4-11 for the cell on its other side.
   const R kappa = (R)g.kappa;
+  double w0[NV];  // V(i,j): the first edge point of both interfaces
+  ldV(g, u.v, i, j, w0);
 #pragma unroll
   for (int dir = 0; dir < 2; ++dir) {
     R Fl[NV];
@@ -797,9 +799,8 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
       } else {
         eval_dir(AN, g, dir, eN);
       }
-      double w0[NV], w1[NV], w2[NV];
+      double w1[NV], w2[NV];
       R dF[NV];
-      ldV(g, u.v, i, j, w0);
       if (dir == 0) {
         ldX(g, u.x, i, j, w1);
         ldV(g, u.v, i, j + 1, w2);
