@@ -87,3 +87,16 @@ def test_bench_algorithmic_bytes_per_cell():
     assert bench.BYTES_PER_CELL_POINTS == pytest.approx(256 + 192 + 192 * 2 / 3)
     assert bench.BYTES_PER_CELL_CELLS == pytest.approx(256 + 64 + 64 * 2 / 3)
     assert bench.BYTES_PER_CELL_STAGE == pytest.approx(256 + 256 + 256 * 2 / 3)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the build runs on one GPU; bench.py --gpus N with N > 1 exits with a
+    # message before touching any device
+    import json
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
