@@ -193,7 +193,17 @@ struct af_mhd_adj {
   size_t ab_doubles;
   size_t tape_bytes;
   hipStream_t stream;
+  // The reverse of the point update runs on an auxiliary stream beside the
+  // reverse of the cell update: the two only add into the shared adjoint
+  // buffers (atomics), and the centre kernels that read them wait for both.
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   std::string err;
+  ~af_mhd_adj() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (aux) (void)hipStreamDestroy(aux);
+  }
 };
 
 namespace {
@@ -238,6 +248,14 @@ int af_mhd_adj_init(const af_mhd_params* p, void* workspace_dev, size_t workspac
   c->ab_doubles = need / sizeof(double);
   c->tape_bytes = tape_layout(g, nullptr, nullptr);
   c->stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    adj_init_err = std::string("af_mhd_adj_init: ") + hipGetErrorString(e);
+    delete c;
+    return AF_EHIP;
+  }
   *out = c;
   return AF_OK;
 }
@@ -260,12 +278,21 @@ int af_mhd_adj_record(af_mhd_adj* c, int k, const af_mhd_state* un, const af_mhd
   hipStream_t s = c->stream;
   (void)hipGetLastError();
   kr_centre<<<nblk((long)g.nx * g.ny), ABLK, 0, s>>>(g, u, t);
+  // fork: the points need only the centre values; they run on the
+  // auxiliary stream beside the cell chain (disjoint outputs and tape fields)
+  hipError_t he = hipEventRecord(c->fork, s);
+  if (he == hipSuccess) he = hipStreamWaitEvent(c->aux, c->fork, 0);
+  if (he != hipSuccess) return fail(c, AF_EHIP, std::string("af_mhd_adj_record: ") + hipGetErrorString(he));
+  kr_points<<<nblk((long)g.nxp * g.ny + (long)g.nx * g.nyp + (long)g.nxp * g.nyp), ABLK, 0, c->aux>>>(
+      g, n, u, t, o, dt_dev, a, b);
+  he = hipEventRecord(c->join, c->aux);
   kr_sensor<<<nblk((long)e.sw * e.sh), ABLK, 0, s>>>(g, u, t);
   kr_iface<<<nblk((long)e.xw * e.xh + (long)e.yw * e.yh), ABLK, 0, s>>>(g, u, t);
   kr_limiter<<<nblk((long)e.ew * e.eh), ABLK, 0, s>>>(g, u, t, dt_dev);
   kr_update<<<nblk((long)g.nx * g.ny), ABLK, 0, s>>>(g, n, u, t, o.a, dt_dev, a, b);
-  kr_points<<<nblk((long)g.nxp * g.ny + (long)g.nx * g.nyp + (long)g.nxp * g.nyp), ABLK, 0, s>>>(g, n, u, t, o,
-                                                                                                 dt_dev, a, b);
+  // join: the stage's output and tape are complete on s
+  if (he == hipSuccess) he = hipStreamWaitEvent(s, c->join, 0);
+  if (he != hipSuccess) return fail(c, AF_EHIP, std::string("af_mhd_adj_record: ") + hipGetErrorString(he));
   return check_hip(c, "af_mhd_adj_record");
 }
 
@@ -289,12 +316,20 @@ int af_mhd_adj_stage(af_mhd_adj* c, int k, const af_mhd_state* uk, const void* t
   (void)hipGetLastError();
   ka_zero<<<nblk((long)c->ab_doubles) < 4096 ? nblk((long)c->ab_doubles) : 4096, ABLK, 0, s>>>(c->ab_base,
                                                                                                 (long)c->ab_doubles);
+  // fork: the points' reverse on the auxiliary stream, the cells' on s
+  hipError_t he = hipEventRecord(c->fork, s);
+  if (he == hipSuccess) he = hipStreamWaitEvent(c->aux, c->fork, 0);
+  if (he != hipSuccess) return fail(c, AF_EHIP, std::string("af_mhd_adj_stage: ") + hipGetErrorString(he));
+  ka_points<<<nblk((long)g.nxp * g.ny + (long)g.nx * g.nyp + (long)g.nxp * g.nyp), ABLK, 0, c->aux>>>(
+      g, u, t, c->ab, lo, ln, lk, dt_dev, a, b);
+  he = hipEventRecord(c->join, c->aux);
   ka_update<<<nblk((long)g.nx * g.ny), ABLK, 0, s>>>(g, t, c->ab, lo, ln, lk, dt_dev, a, b);
   ka_limiter<<<nblk((long)e.ew * e.eh), ABLK, 0, s>>>(g, u, t, c->ab, lk, dt_dev);
   ka_iface<<<nblk((long)e.xw * e.xh + (long)e.yw * e.yh), ABLK, 0, s>>>(g, u, t, c->ab, lk);
   ka_sensor<<<nblk((long)e.sw * e.sh), ABLK, 0, s>>>(g, u, t, c->ab, lk);
-  ka_points<<<nblk((long)g.nxp * g.ny + (long)g.nx * g.nyp + (long)g.nxp * g.nyp), ABLK, 0, s>>>(
-      g, u, t, c->ab, lo, ln, lk, dt_dev, a, b);
+  // join: the centre kernels read what both sides added
+  if (he == hipSuccess) he = hipStreamWaitEvent(s, c->join, 0);
+  if (he != hipSuccess) return fail(c, AF_EHIP, std::string("af_mhd_adj_stage: ") + hipGetErrorString(he));
   ka_centre<<<nblk((long)g.nx * g.ny), ABLK, 0, s>>>(g, u, t, c->ab, lk);
   ka_centre_gather<<<nblk((long)g.nxp * g.ny + (long)g.nx * g.nyp + (long)g.nxp * g.nyp), ABLK, 0, s>>>(g, c->ab, lk);
   return check_hip(c, "af_mhd_adj_stage");
