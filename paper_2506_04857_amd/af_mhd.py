@@ -422,6 +422,29 @@ class CheckpointedRun:
 
         return tuple(torch.zeros(s, dtype=torch.float64, device=self.device) for s in self.prob.shapes())
 
+    def _empty(self):
+        import torch
+
+        return tuple(torch.empty(s, dtype=torch.float64, device=self.device) for s in self.prob.shapes())
+
+    def _zero_states(self, n: int):
+        """n zeroed states carved from one buffer (one fill launch)."""
+        import math
+
+        import torch
+
+        shapes = self.prob.shapes()
+        sizes = [math.prod(s) for s in shapes]
+        buf = torch.zeros(n * sum(sizes), dtype=torch.float64, device=self.device)
+        out, off = [], 0
+        for _ in range(n):
+            st = []
+            for s, m in zip(shapes, sizes):
+                st.append(buf[off:off + m].view(s))
+                off += m
+            out.append(tuple(st))
+        return out
+
     def forward(self, u0, nsteps: int, dts=None, t_final: float = float("inf")):
         """Returns the end state (new tensors).  dts: a device tensor of fixed
         step sizes to use instead of the CFL rule."""
@@ -466,7 +489,8 @@ class CheckpointedRun:
             u = self.checkpoints[c]
             for s in range(first, last):
                 d = self.dts[s:s + 1]
-                u1, u2, u3 = self._zeros(), self._zeros(), self._zeros()
+                # the recording stage writes every element of its output
+                u1, u2, u3 = self._empty(), self._empty(), self._empty()
                 t0, t1, t2 = self.adj.new_tape(), self.adj.new_tape(), self.adj.new_tape()
                 self.adj.record(0, u, u, u1, d, t0)
                 self.adj.record(1, u, u1, u2, d, t1)
@@ -474,7 +498,8 @@ class CheckpointedRun:
                 hist.append((u, u1, u2, t0, t1, t2, d))
                 u = u3
             for un, u1, u2, t0, t1, t2, d in reversed(hist):
-                ln, l2, l1 = self._zeros(), self._zeros(), self._zeros()
+                # the sweep adds into its accumulators
+                ln, l2, l1 = self._zero_states(3)
                 self.adj.stage(2, u2, t2, d, lam, ln, l2)
                 self.adj.stage(1, u1, t1, d, l2, ln, l1)
                 self.adj.stage(0, un, t0, d, l1, None, ln)
