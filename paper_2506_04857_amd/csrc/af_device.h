@@ -265,8 +265,9 @@ __device__ void limit_point(const double UH[NV], const double UL[NV], double gm1
   const double rhoL = UL[0];
   const double er = fmin(EPS_FLOOR, rhoL);
   // common case: the LLF state has p >= 1e-13 (so eps_p = 1e-13) and the
-  // high-order state satisfies both bounds: no limiting, no division
-  if (rhoL > 0.0 && p_at_least(UL, EPS_FLOOR, gm1) && UH[0] >= er && p_at_least(UH, EPS_FLOOR, gm1)) {
+  // high-order state satisfies both bounds: no limiting, no division (the
+  // four tests are combined without short circuits: one branch, not four)
+  if ((rhoL > 0.0) & p_at_least(UL, EPS_FLOOR, gm1) & (UH[0] >= er) & p_at_least(UH, EPS_FLOOR, gm1)) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) W[c] = UH[c];
     return;
@@ -310,7 +311,7 @@ __device__ void limit_centre(const double Uc[NV], const double A[NV], double gm1
                              bool counted) {
   const double rhoA = A[0];
   const double er = fmin(EPS_FLOOR, rhoA);
-  if (rhoA > 0.0 && p_at_least(A, EPS_FLOOR, gm1) && Uc[0] >= er && p_at_least(Uc, EPS_FLOOR, gm1)) {
+  if ((rhoA > 0.0) & p_at_least(A, EPS_FLOOR, gm1) & (Uc[0] >= er) & p_at_least(Uc, EPS_FLOOR, gm1)) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) C[c] = Uc[c];
     return;

@@ -785,13 +785,14 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
       DirEvalT<R> eA, eN;
       double AN[NV];
       R q[4];
+      // the neighbour's average is loaded first: in flight across the barrier
+      if (dir == 0) ldA(g, u.a, i - 1, j, AN); else ldA(g, u.a, i, j - 1, AN);
       rec_eval(A, g, dir, q);
 #pragma unroll
       for (int c = 0; c < 4; ++c) s_x[c][ty][tx] = q[c];
       rec_rebuild_d(A, dir, q, eA);
       __syncthreads();
       const int nx_ = dir == 0 ? tx - 1 : tx, ny_ = dir == 0 ? ty : ty - 1;
-      if (dir == 0) ldA(g, u.a, i - 1, j, AN); else ldA(g, u.a, i, j - 1, AN);
       if ((dir == 0 ? tx : ty) > 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) q[c] = s_x[c][ny_][nx_];
