@@ -345,22 +345,14 @@ Vec point_scaling_limiter(const Vec& UH, const Vec& UL, double gamma, Counters& 
   return make(th2);
 }
 
-// Centre value of the bi-parabolic reconstruction (Section 2.1) and its
-// limiter (Remark rmk:cell_center).  Reading: the limited centre is
-// theta~ Uc + (1 - theta~) Abar with theta~ = theta_rho * theta_p: first the
-// whole state is blended towards the cell average until rho >= eps_rho, then
-// again until p >= eps_p; eps from the cell average.
-Vec centre_value(const Access& acc, int i, int j, double gamma, Counters& cnt) {
-  const Vec A = acc.A(i, j);
-  const Vec Xl = acc.X(i, j), Xr = acc.X(i + 1, j);
-  const Vec Yd = acc.Y(i, j), Yu = acc.Y(i, j + 1);
-  const Vec Vdl = acc.V(i, j), Vdr = acc.V(i + 1, j), Vul = acc.V(i, j + 1), Vur = acc.V(i + 1, j + 1);
-  Vec Uc;
-  for (int c = 0; c < NV; ++c) {
-    const real faces = (Xl[c] + Xr[c]) + (Yd[c] + Yu[c]);
-    const real corners = (Vdl[c] + Vdr[c]) + (Vul[c] + Vur[c]);
-    Uc[c] = (36.0 * A[c] - 4.0 * faces - corners) / 16.0;
-  }
+// Limiter of the centre value, Remark rmk:cell_center: the limited centre is
+// of the printed form theta~ Uc + (1 - theta~) Abar, one coefficient for the
+// whole state.  Reading: theta~ = theta_rho * theta_p, found like the point
+// limiter's two steps -- first the whole state is blended towards the cell
+// average until rho >= eps_rho, then again until p >= eps_p; eps from the
+// cell average.  The round-off fallback of the closing remark of Section 4
+// acts on theta_p.
+Vec centre_limiter(const Vec& Uc, const Vec& A, double gamma, Counters& cnt) {
   const real rhoA = A[0], pA = pressure(A, gamma);
   const real eps_rho = std::min<real>(EPS_FLOOR, rhoA);
   const real eps_p = std::min<real>(EPS_FLOOR, pA);
@@ -379,6 +371,23 @@ Vec centre_value(const Access& acc, int i, int j, double gamma, Counters& cnt) {
   };
   th2 = shrink_until_admissible(th2, gamma, make, cnt);
   return make(th2);
+}
+
+// Centre value of the bi-parabolic reconstruction (Section 2.1),
+//   Uc = (36 Abar - 4 (sum of the face midpoints) - (sum of the vertices)) / 16,
+// then limited towards the cell average.
+Vec centre_value(const Access& acc, int i, int j, double gamma, Counters& cnt) {
+  const Vec A = acc.A(i, j);
+  const Vec Xl = acc.X(i, j), Xr = acc.X(i + 1, j);
+  const Vec Yd = acc.Y(i, j), Yu = acc.Y(i, j + 1);
+  const Vec Vdl = acc.V(i, j), Vdr = acc.V(i + 1, j), Vul = acc.V(i, j + 1), Vur = acc.V(i + 1, j + 1);
+  Vec Uc;
+  for (int c = 0; c < NV; ++c) {
+    const real faces = (Xl[c] + Xr[c]) + (Yd[c] + Yu[c]);
+    const real corners = (Vdl[c] + Vdr[c]) + (Vul[c] + Vur[c]);
+    Uc[c] = (36.0 * A[c] - 4.0 * faces - corners) / 16.0;
+  }
+  return centre_limiter(Uc, A, gamma, cnt);
 }
 
 // ------------------------------------------- point value update (Sec. 2.3)
@@ -616,7 +625,7 @@ real vertex_root(const Vec& A1, const Vec& D, double gamma, real eps_p, int& ite
 // Lambda^rho and the pressure shrink over the 15 non-trivial vertices.
 // H[0..3] = H_L, H_R, H_D, H_U.  Returns Lambda[0..3].
 void flux_limiter_box(const Vec& A1, const Vec H[4], double gamma, real eps_rho, real eps_p,
-                      real Lambda[4], Counters& cnt) {
+                      real Lambda[4], Counters& cnt, real* before_fallback = nullptr) {
   real neg = 0.0;
   for (int I = 0; I < 4; ++I)
     if (H[I][0] < 0.0) neg += H[I][0];
@@ -646,6 +655,8 @@ void flux_limiter_box(const Vec& A1, const Vec H[4], double gamma, real eps_rho,
       if (k & (1 << I)) rmin[I] = std::min(rmin[I], r);
   }
   for (int I = 0; I < 4; ++I) Lambda[I] = Lr[I] * rmin[I];
+  if (before_fallback)
+    for (int I = 0; I < 4; ++I) before_fallback[I] = Lambda[I];
   if (!any_root) return;  // the box corners are exactly the vertices checked above
   // Round-off fallback on the final box: all 15 corners must lie in G.
   auto box_ok = [&](const real L[4]) {
@@ -1270,16 +1281,28 @@ void orc_point_limiter(const double* UH, const double* UL, double gamma, double*
   if (n_fallback) *n_fallback = c.n_fallback;
 }
 // Flux limiter step (2): A1[8], H[4][8] -> Lambda[4].
+// Lambda_pre[4] (may be null): the box before the round-off fallback.
 void orc_flux_limiter_box(const double* A1, const double* H, double gamma, double eps_rho, double eps_p,
-                          double* Lambda, int64_t* n_newton, int64_t* iters_max, int64_t* n_fallback) {
+                          double* Lambda, int64_t* n_newton, int64_t* iters_max, int64_t* n_fallback,
+                          double* Lambda_pre) {
   Vec a;
   std::memcpy(a.data(), A1, sizeof(Vec));
   Vec h[4];
   for (int I = 0; I < 4; ++I) std::memcpy(h[I].data(), H + 8 * I, sizeof(Vec));
   Counters c;
-  flux_limiter_box(a, h, gamma, eps_rho, eps_p, Lambda, c);
+  flux_limiter_box(a, h, gamma, eps_rho, eps_p, Lambda, c, Lambda_pre);
   if (n_newton) *n_newton = c.n_newton;
   if (iters_max) *iters_max = c.newton_iters_max;
+  if (n_fallback) *n_fallback = c.n_fallback;
+}
+// Limiter of a centre value Uc towards the cell average A.
+void orc_centre_limiter(const double* Uc, const double* A, double gamma, double* out, int64_t* n_fallback) {
+  Vec u, a;
+  std::memcpy(u.data(), Uc, sizeof(Vec));
+  std::memcpy(a.data(), A, sizeof(Vec));
+  Counters c;
+  const Vec w = centre_limiter(u, a, gamma, c);
+  std::memcpy(out, w.data(), sizeof(Vec));
   if (n_fallback) *n_fallback = c.n_fallback;
 }
 double orc_vertex_root(const double* A1, const double* D, double gamma, double eps_p, int* iters) {

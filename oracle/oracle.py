@@ -127,7 +127,8 @@ def lib():
         L.orc_point_limiter.argtypes = [_D, _D, ctypes.c_double, _D, ctypes.POINTER(ctypes.c_int64)]
         L.orc_flux_limiter_box.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                                           ctypes.POINTER(ctypes.c_int64)]
+                                           ctypes.POINTER(ctypes.c_int64), _D]
+        L.orc_centre_limiter.argtypes = [_D, _D, ctypes.c_double, _D, ctypes.POINTER(ctypes.c_int64)]
         L.orc_vertex_root.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
         L.orc_vertex_root.restype = ctypes.c_double
         L.orc_point_llf.argtypes = [_D, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -261,13 +262,26 @@ def point_limiter(uh, ul, gamma):
 
 
 def flux_limiter_box(a1, H, gamma, eps_rho, eps_p):
+    """Step (2) of the flux limiter.  Returns (Lambda[4], info) with info's
+    ``lambda_before_fallback`` the box before the round-off fallback."""
     H = np.ascontiguousarray(H, dtype=np.float64)
     assert H.shape == (4, 8)
     lam = np.zeros(4)
+    pre = np.zeros(4)
     nn, it, nf = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     lib().orc_flux_limiter_box(_ptr(_vec(a1)), _ptr(H), gamma, eps_rho, eps_p, _ptr(lam), ctypes.byref(nn),
-                               ctypes.byref(it), ctypes.byref(nf))
-    return lam, {"n_newton": nn.value, "iters_max": it.value, "n_fallback": nf.value}
+                               ctypes.byref(it), ctypes.byref(nf), _ptr(pre))
+    return lam, {"n_newton": nn.value, "iters_max": it.value, "n_fallback": nf.value,
+                 "lambda_before_fallback": pre}
+
+
+def centre_limiter(uc, a, gamma):
+    """The centre value uc limited towards the cell average a; returns
+    (limited state, n_fallback)."""
+    out = np.zeros(8)
+    nf = ctypes.c_int64(0)
+    lib().orc_centre_limiter(_ptr(_vec(uc)), _ptr(_vec(a)), gamma, _ptr(out), ctypes.byref(nf))
+    return out, nf.value
 
 
 def vertex_root(a1, d, gamma, eps_p):
