@@ -1,14 +1,22 @@
 """Benchmark: cell-updates per second per SSP-RK3 stage of the PP Active
-Flux MHD scheme on one MI355X (FP64), Orszag-Tang vortex on a 512x512
-periodic grid (synthetic initial data; inputs resident in HBM before the
-timed region).
+Flux MHD scheme on one MI355X (FP64), low-beta blast on a 1024x1024 outflow
+grid (synthetic initial data; inputs resident in HBM before the timed
+region; the state sets, 1.07 GB per step with U^n, U^(k) and the output,
+are past the 256 MB Infinity Cache).
 
-python bench.py [--steps K] [--warmup W] [--workload orszag_tang_512|blast_lowbeta_1024|alfven_32]
+python bench.py [--steps K] [--warmup W] [--workload blast_lowbeta_1024|orszag_tang_512|alfven_32]
 Prints one JSON line.
 
-Also measured (objects of the same line): the batched ensemble, the FP32-bulk
-stage, the adjoint workload (adjoint/forward time, finite-difference and
-oracle-reference checks of the gradient) and the CPU oracle baseline.
+roofline: the whole stage against HBM -- the stage's algorithmic bytes
+(682.7 B per cell, mean over the three stages) over the average device time
+of one stage's kernels (point kernel + cell kernel + a third of the step's
+time-step reduction), from HIP events on the launch stream.
+
+Also measured (objects of the same line): the FP32-bulk stage, the
+Orszag-Tang 512^2 workload, the batched ensemble, the adjoint workload
+(adjoint/forward time, finite-difference and oracle-reference checks of the
+gradient) and the CPU oracle baseline (single-threaded and on all host
+cores).
 
 python bench.py --copy-calibration MIB
 runs a plain device-to-device copy of MIB MiB three times (the known-size
@@ -40,7 +48,13 @@ BYTES_PER_CELL_CELLS = 256 + 64 * 2.0 / 3.0 + 64
 #   point kernel: read U^(k) 256, read X^n, Y^n, V^n 192 (k >= 1), write 192
 BYTES_PER_CELL_POINTS = 256 + 192 * 2.0 / 3.0 + 192
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_points_k_cells_orszag_tang_512_hbm_traffic.txt")
+# rocprofv3 summaries of the stage kernels per workload (committed under
+# profiles/): HBM traffic (FETCH_SIZE, WRITE_SIZE) and VALU instruction counts
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILES = {"blast_lowbeta_1024": "k_points_k_cells_blast_lowbeta_1024_hbm_traffic.txt",
+                 "orszag_tang_512": "k_points_k_cells_orszag_tang_512_hbm_traffic.txt"}
+VALU_FILES = {"blast_lowbeta_1024": "k_points_k_cells_blast_lowbeta_1024_valu.txt"}
+CUS, CLOCK_HZ = 256, 2.4e9  # MI355X: one wave-instruction issued per CU per cycle at most
 
 
 # The sources the stage kernels k_points / k_cells are built from (the
@@ -58,42 +72,69 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of the kernel from the committed rocprofv3
-    counter summary, or None when it is missing, for another workload, or
-    taken from a different kernel source."""
-    if workload != "orszag_tang_512" or not os.path.exists(TRAFFIC_FILE):
+def profile_values(fname: str):
+    """key: value pairs of a committed profile summary, or None when it is
+    missing or was taken from a different kernel source."""
+    path = os.path.join(PROFILES, fname)
+    if not fname or not os.path.isfile(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("source_sha256") != source_hash():
         return None
+    return kv
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of the kernel from the committed rocprofv3
+    counter summary, or None."""
+    kv = profile_values(TRAFFIC_FILES.get(workload, ""))
     try:
-        return float(kv["traffic_bytes_per_launch." + kernel + "<double>"])
-    except (KeyError, ValueError):
+        return float(kv["traffic_bytes_per_launch." + kernel])
+    except (TypeError, KeyError, ValueError):
         return None
 
 
-def cpu_baseline(prob, u0, budget_s=12.0):
-    """The CPU oracle timed on a bounded sample of the same workload."""
+def measured_valu(workload: str, kernel: str):
+    """VALU wave-instructions per launch of the kernel from the committed
+    SQ counter summary, or None."""
+    kv = profile_values(VALU_FILES.get(workload, ""))
+    try:
+        return float(kv["valu_insts_per_launch." + kernel])
+    except (TypeError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(prob, u0, budget_s=10.0):
+    """The CPU oracle timed on a bounded sample of the same workload:
+    forward-Euler stages from the initial data, single-threaded and with
+    OpenMP over rows on all the host cores it is given."""
     from oracle import oracle as orc
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    dt = orc.dt(prob, u0, nthreads=threads)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        orc.stage(prob, 0, u0, u0, dt, nthreads=threads)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    el = time.perf_counter() - t0
-    return {"value": prob.nx * prob.ny * n / el, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": f"{n} forward-Euler stages of {prob.name} {prob.nx}x{prob.ny} from the initial data "
-                      f"in {el:.1f} s (FP64 C++ oracle, OpenMP over rows)"}
+
+    def rate(nthreads):
+        dt = orc.dt(prob, u0, nthreads=nthreads)
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            orc.stage(prob, 0, u0, u0, dt, nthreads=nthreads)
+            n += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        el = time.perf_counter() - t0
+        return prob.nx * prob.ny * n / el, n, el
+
+    v_all, n_all, el_all = rate(threads)
+    v_one, n_one, el_one = rate(1)
+    return {"value": v_all, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "single_thread": {"value": v_one, "unit": UNIT, "cores": 1},
+            "sample": f"forward-Euler stages of {prob.name} {prob.nx}x{prob.ny} from the initial data (FP64 C++ "
+                      f"oracle): {n_all} stages in {el_all:.1f} s on {threads} threads (OpenMP over rows), "
+                      f"{n_one} in {el_one:.1f} s on one"}
 
 
 def copy_calibration(mib: int):
@@ -261,7 +302,7 @@ def adjoint(af, I, args):
     grad()  # warm-up (kernel loading, allocator)
     g, dts, fwd_ckpt_ms, bwd_ms, J, tape_bytes = grad()
     # the plain forward: 400 whole steps of the stage kernels, no checkpoints
-    ctx = af.Context(prob)
+    ctx = af.Context(prob, flags=af.AF_FLAG_FUSED_DT)
     u = af.to_device(u0)
     fwd_ms = timed_steps(ctx, u, nsteps, ctx.stream)
     ctx.close()
@@ -293,16 +334,47 @@ def adjoint(af, I, args):
     return out
 
 
+def stage_run(af, prob, u0, args, flags):
+    """Timed region: K whole steps (time step + three stages) after W
+    warm-up steps, no timing events; then the same with per-kernel HIP
+    events on the launch stream (AF_FLAG_KERNEL_TIMING) for the kernels'
+    average launch durations.  The step's time step is the fused one
+    (AF_FLAG_FUSED_DT: the last stage leaves the wave-speed maxima).
+    Returns (ms for K steps, stats, final state, average us per launch)."""
+    flags |= af.AF_FLAG_FUSED_DT
+    ctx = af.Context(prob, flags=flags)
+    u = af.to_device(u0)
+    for _ in range(args.warmup):
+        ctx.af_mhd_step(u)
+    ms = timed_steps(ctx, u, args.steps, ctx.stream)
+    st = ctx.af_mhd_stats(u)
+    ctx.close()
+    tctx = af.Context(prob, flags=flags | af.AF_FLAG_KERNEL_TIMING)
+    v = af.to_device(u0)
+    for _ in range(args.warmup):
+        tctx.af_mhd_step(v)
+    tctx.af_mhd_kernel_times(reset=True)
+    timed_steps(tctx, v, args.steps, tctx.stream)
+    kt = tctx.af_mhd_kernel_times()
+    tctx.close()
+    us = {"k_cells": 1e3 * kt["ms_cells"] / max(kt["n_cells"], 1),
+          "k_points": 1e3 * kt["ms_points"] / max(kt["n_points"], 1),
+          "dt": 1e3 * kt["ms_dt"] / max(kt["n_dt"], 1)}
+    return ms, st, af.to_host(u), us
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="orszag_tang_512")
+    ap.add_argument("--workload", default="blast_lowbeta_1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra workloads (FP32-bulk, Orszag-Tang 512^2, graph replay, stream copy)")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint measurement (its JSON object)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched-ensemble measurement (its JSON object), e.g. for profiling it")
@@ -332,78 +404,32 @@ def main():
     cells = prob.nx * prob.ny
     stages = 3 * args.steps
 
-    def run(flags):
-        """Timed region: K whole steps (dt reduction + three stages) after W
-        warm-up steps, no timing events; then the same with per-kernel HIP
-        events on the launch stream (AF_FLAG_KERNEL_TIMING) for the kernels'
-        average launch durations.  Returns (ms, stats, final state, us)."""
-        ctx = af.Context(prob, flags=flags)
-        u = af.to_device(u0)
-        for _ in range(args.warmup):
-            ctx.af_mhd_step(u)
-        ms = timed_steps(ctx, u, args.steps, ctx.stream)
-        st = ctx.af_mhd_stats(u)
-        ctx.close()
-        tctx = af.Context(prob, flags=flags | af.AF_FLAG_KERNEL_TIMING)
-        v = af.to_device(u0)
-        for _ in range(args.warmup):
-            tctx.af_mhd_step(v)
-        tctx.af_mhd_kernel_times(reset=True)
-        timed_steps(tctx, v, args.steps, tctx.stream)
-        kt = tctx.af_mhd_kernel_times()
-        tctx.close()
-        us = {"k_cells": 1e3 * kt["ms_cells"] / max(kt["n_cells"], 1),
-              "k_points": 1e3 * kt["ms_points"] / max(kt["n_points"], 1),
-              "dt": 1e3 * kt["ms_dt"] / max(kt["n_dt"], 1)}
-        return ms, st, af.to_host(u), us
-
-    ms, st, u64, us = run(0)
+    ms, st, u64, us = stage_run(af, prob, u0, args, 0)
     t_stage = ms * 1e-3 / stages
     value = cells / t_stage
 
-    # the same steps replayed from a hipGraph (a one-instance batch): what
-    # launch-bound small grids gain
-    import torch
-    gstates = [af.to_device(u0)]
-    gb = af.Batch([prob], gstates)
-    for _ in range(args.warmup):
-        gb.step()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(gb.stream)
-    for _ in range(args.steps):
-        gb.step()
-    e1.record(gb.stream)
-    torch.cuda.synchronize()
-    graph_value = cells / (e0.elapsed_time(e1) * 1e-3 / stages)
-    gb.close()
-    del gstates
-
-    # FP32-bulk stage on the same workload, and its difference from the
-    # FP64 run after the same number of steps (L1 of rho and p, relative)
-    ms32, st32, u32, us32 = run(af.AF_FLAG_FP32_BULK)
-    value32 = cells / (ms32 * 1e-3 / stages)
-
-    def pressure(A):
-        return (prob.gamma - 1) * (A[7] - 0.5 * (A[1] ** 2 + A[2] ** 2 + A[3] ** 2) / A[0]
-                                   - 0.5 * (A[4] ** 2 + A[5] ** 2 + A[6] ** 2))
-
-    l1_rho = float(abs(u32[0][0] - u64[0][0]).mean() / abs(u64[0][0]).mean())
-    p64, p32 = pressure(u64[0]), pressure(u32[0])
-    l1_p = float(abs(p32 - p64).mean() / abs(p64).mean())
-    # the dominant kernel: the larger of the two stage kernels; both are
-    # reported under per_kernel (they take about the same time)
+    # roofline: the whole stage (both kernels and a third of the step's time
+    # step) against HBM, by the stage's algorithmic bytes
+    stage_bytes = BYTES_PER_CELL_STAGE * cells
+    stage_us = us["k_points"] + us["k_cells"] + us["dt"] / 3.0
+    achieved = stage_bytes / (stage_us * 1e-6) / 1e9
     per_kernel = {}
     for kname, bpc in (("k_points", BYTES_PER_CELL_POINTS), ("k_cells", BYTES_PER_CELL_CELLS)):
         a = bpc * cells / (us[kname] * 1e-6) / 1e9
         per_kernel[kname] = {"achieved": a, "frac": a / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bpc * cells,
-                             "avg_launch_us": us[kname], "traffic": measured_traffic(args.workload, kname)}
-    dom = "k_points" if us["k_points"] >= us["k_cells"] else "k_cells"
-    algo = per_kernel[dom]["algorithmic_bytes_per_launch"]
-    achieved = per_kernel[dom]["achieved"]
-    traffic = per_kernel[dom]["traffic"]
+                             "avg_launch_us": us[kname],
+                             "traffic": measured_traffic(args.workload, kname + "<double>")}
+    parts = [measured_traffic(args.workload, k) for k in ("k_points<double>", "k_cells<double>", "k_dt_from_parts")]
+    traffic = None if any(p is None for p in parts) else parts[0] + parts[1] + parts[2] / 3.0
+    # VALU issue: wave-instructions per cell-stage against one per CU per cycle
+    vparts = [measured_valu(args.workload, k) for k in ("k_points<double>", "k_cells<double>")]
+    valu = None
+    if all(v is not None for v in vparts):
+        wi = (vparts[0] + vparts[1]) / cells
+        limit = CUS * CLOCK_HZ / wi
+        valu = {"wave_instr_per_cell_stage": wi, "issue_limited_value": limit, "frac": value / limit,
+                "peak": "256 CUs x 2.4 GHz, one wave-instruction per CU per cycle"}
 
-    copy = stream_copy_gbs(af)
     out = {
         "metric": METRIC,
         "value": value,
@@ -420,22 +446,64 @@ def main():
         "config": {"workload": f"{prob.name} {prob.nx}x{prob.ny}", "nx": prob.nx, "ny": prob.ny,
                    "cells": cells, "cfl": prob.cfl, "kappa": prob.kappa,
                    "boundary": "periodic" if prob.bc_x == 0 else "outflow"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": algo, "avg_launch_us": us[dom], "per_kernel": per_kernel},
+        "roofline": {"bound": "hbm", "kernel": "stage: k_points + k_cells + 1/3 of the step's dt reduction",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": stage_bytes,
+                     "algorithmic_bytes_per_cell": BYTES_PER_CELL_STAGE, "avg_stage_us": stage_us,
+                     "valu": valu, "per_kernel": per_kernel},
         "kernels_us": us,
-        "graph_step_value": graph_value,
-        "stage_hbm_gbs": BYTES_PER_CELL_STAGE * cells / t_stage / 1e9,
-        "stream_copy": {"gbs": copy["gbs"], "buffer_bytes": copy["bytes"],
-                        "dominant_kernel_frac": achieved / copy["gbs"],
-                        "stage_frac": BYTES_PER_CELL_STAGE * cells / t_stage / 1e9 / copy["gbs"]},
+        "stage_hbm_gbs": stage_bytes / t_stage / 1e9,
         "admissible": bool(st["admissible"]),
-        "fp32_bulk": {"value": value32, "unit": UNIT, "speedup_vs_fp64": value32 / value,
-                      "ms_per_step": ms32 / args.steps, "kernels_us": us32,
-                      "admissible": bool(st32["admissible"]),
-                      "l1_rel_vs_fp64": {"rho": l1_rho, "p": l1_p},
-                      "compared_after_steps": args.warmup + args.steps},
     }
+    if not args.no_extra:
+        import torch
+        # the same steps replayed from a hipGraph (a one-instance batch)
+        gstates = [af.to_device(u0)]
+        gb = af.Batch([prob], gstates)
+        for _ in range(args.warmup):
+            gb.step()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(gb.stream)
+        for _ in range(args.steps):
+            gb.step()
+        e1.record(gb.stream)
+        torch.cuda.synchronize()
+        out["graph_step_value"] = cells / (e0.elapsed_time(e1) * 1e-3 / stages)
+        gb.close()
+        del gstates
+
+        # FP32-bulk stage on the same workload, and its difference from the
+        # FP64 run after the same number of steps (L1 of rho and p, relative)
+        ms32, st32, u32, us32 = stage_run(af, prob, u0, args, af.AF_FLAG_FP32_BULK)
+        value32 = cells / (ms32 * 1e-3 / stages)
+
+        def pressure(A):
+            return (prob.gamma - 1) * (A[7] - 0.5 * (A[1] ** 2 + A[2] ** 2 + A[3] ** 2) / A[0]
+                                       - 0.5 * (A[4] ** 2 + A[5] ** 2 + A[6] ** 2))
+
+        l1_rho = float(abs(u32[0][0] - u64[0][0]).mean() / abs(u64[0][0]).mean())
+        p64, p32 = pressure(u64[0]), pressure(u32[0])
+        l1_p = float(abs(p32 - p64).mean() / abs(p64).mean())
+        out["fp32_bulk"] = {"value": value32, "unit": UNIT, "speedup_vs_fp64": value32 / value,
+                            "ms_per_step": ms32 / args.steps, "kernels_us": us32,
+                            "admissible": bool(st32["admissible"]),
+                            "min_rho": st32["min_rho"], "min_p": st32["min_p"],
+                            "l1_rel_vs_fp64": {"rho": l1_rho, "p": l1_p},
+                            "compared_after_steps": args.warmup + args.steps}
+
+        # the Orszag-Tang vortex 512^2 (periodic; its states fit the 256 MB
+        # Infinity Cache, so its rates are effective rates)
+        if args.workload != "orszag_tang_512":
+            ot = I.orszag_tang(512)
+            ms_ot, st_ot, _, us_ot = stage_run(af, ot, I.sample(ot), args, 0)
+            out["orszag_tang_512"] = {"value": ot.nx * ot.ny / (ms_ot * 1e-3 / stages), "unit": UNIT,
+                                      "ms_per_step": ms_ot / args.steps, "kernels_us": us_ot,
+                                      "admissible": bool(st_ot["admissible"])}
+
+        copy = stream_copy_gbs(af)
+        out["stream_copy"] = {"gbs": copy["gbs"], "buffer_bytes": copy["bytes"],
+                              "stage_frac": achieved / copy["gbs"]}
     if not args.no_batch:
         out["batched"] = batched(af, I, args)
     if not args.no_adjoint:

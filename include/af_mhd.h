@@ -78,6 +78,17 @@ typedef struct {
  * event record per launch boundary; off by default. */
 #define AF_FLAG_KERNEL_TIMING 4u
 
+/* Time-step reduction fused into the epilogue of a step's last stage:
+ * af_mhd_step leaves, per workgroup of its stage-2 kernels, the maximum of
+ * rho_1/dx + rho_2/dy over the values it stores, and the next af_mhd_step
+ * on the same state (same four pointers) takes dt from those maxima alone
+ * instead of re-reading the whole state.  dt is bitwise the one af_mhd_dt
+ * computes from that state.  Contract: between the two calls the caller
+ * does not change the state other than through af_mhd_step; a step on
+ * another state or any af_mhd_stage call on the context falls back to the
+ * full reduction.  Off by default. */
+#define AF_FLAG_FUSED_DT 8u
+
 typedef struct {            /* device time since init or the last reset */
   double ms_points;         /* point-value kernel (V, X, Y update) */
   double ms_cells;          /* cell-average kernel */
@@ -123,7 +134,11 @@ int af_mhd_init(const af_mhd_params* p, void* workspace_dev, size_t workspace_by
                 af_mhd_ctx** out);
 
 /* Time step from the state u: dt = min(cfl / max_DoF(rho_1/dx + rho_2/dy),
- * t_remaining), written to dt_dev (one device double).  t_remaining > 0. */
+ * t_remaining), written to dt_dev (one device double).  t_remaining > 0.
+ * The paper states no time-step rule (a Lemma of Section 3.1 only bounds
+ * the CFL number of its first-order scheme); this is the reading used:
+ * rho_l = |v_l| + c_f,l, the spectral radius of dF_l/dU (Section 2.3), over
+ * every cell average and point value. */
 int af_mhd_dt(af_mhd_ctx* c, const af_mhd_state* u, double t_remaining, double* dt_dev);
 
 /* One SSP-RK3 stage: out = a_k un + b_k FE(uk, dt) with (a,b) = (0,1),
@@ -134,8 +149,14 @@ int af_mhd_dt(af_mhd_ctx* c, const af_mhd_state* u, double t_remaining, double* 
 int af_mhd_stage(af_mhd_ctx* c, int k, const af_mhd_state* un, const af_mhd_state* uk, af_mhd_state* out,
                  const double* dt_dev);
 
-/* One SSP-RK3 step in place on u: af_mhd_dt then the three stages, using
- * the workspace's scratch states.  The dt used is left in dt_dev. */
+/* One SSP-RK3 step in place on u (SSP-RK3 of Section 2 in Shu-Osher form):
+ * the time step, then the three stages af_mhd_stage k = 0, 1, 2, using the
+ * workspace's scratch states.  The paper gives no time-step rule; the
+ * reading used is dt = min(cfl / max over all DoFs of (rho_1/dx +
+ * rho_2/dy), t_remaining) with rho_l = |v_l| + c_f,l (eq. (cf)), from U^n
+ * and fixed over the three stages (as af_mhd_dt).  With AF_FLAG_FUSED_DT
+ * the maximum comes from the previous step's last stage (see there).  The
+ * dt used is left in dt_dev.  t_remaining > 0. */
 int af_mhd_step(af_mhd_ctx* c, af_mhd_state* u, double t_remaining, double* dt_dev);
 
 /* Statistics of u and the counters accumulated since af_mhd_init.
@@ -166,6 +187,44 @@ void af_mhd_destroy(af_mhd_ctx* c);
  * attainable-bandwidth reference the stage kernels are compared with.  Not a
  * step of the method: a measurement aid.  AF_EINVAL on bad pointers or odd n. */
 int af_mhd_stream_copy(const double* src, double* dst, size_t n, void* hip_stream);
+
+/* ------------------------------------------------------------ limiters
+ * The stage's positivity limiters applied to n given inputs, one device
+ * thread per item, with the same device code the stage kernels run:
+ *   AF_LIM_POINT   scaling limiter of a point value (Section 3.3):
+ *                  in [n][16] = (U^H, U^LLF), out [n][8] = limited value
+ *   AF_LIM_CENTRE  limiter of the centre value towards the cell average
+ *                  (remark rmk:cell_center; one coefficient for the whole
+ *                  state, density step then pressure step):
+ *                  in [n][16] = (centre value, cell average), out [n][8]
+ *   AF_LIM_SOURCE  step (1) of the parametrized flux limiter (Section 3.2):
+ *                  in [n][25] = (G, S^s, S^LLF, dt) with A^LLF = G - dt S^LLF,
+ *                  A^src = G - dt S^s; out [n][9] = (A^{Lim,1}, theta_src)
+ *   AF_LIM_BOX     step (2): density box and the pressure shrink over the 15
+ *                  non-trivial vertices; in [n][42] = (A^{Lim,1}, H_L, H_R,
+ *                  H_D, H_U, eps_rho, eps_p), out [n][4] = Lambda_{L,R,D,U}
+ * Each applies the round-off fallback of the closing remark of Section 4
+ * (coefficient shrunk by 2^m 1e-8, m = 0..9, each trial from the original
+ * value, floored at 0, when the limited state falls outside G).  Limiter
+ * coefficients and every in-G decision use p = (gamma-1)(E - |m|^2/(2 rho)
+ * - |B|^2/2) summed left to right without fused multiply-adds, so identical
+ * inputs give a reference's results bit for bit.  AF_LIM_NO_SHORTCUT (box
+ * only): test all 15 vertices even where the sufficient convexity test
+ * (A^{Lim,1} and the four points A^{Lim,1} + 4 Lambda^rho_I H_I admissible)
+ * already shows that none needs a root, as a reference without that test
+ * does.  gamma > 1.  in_dev, out_dev: device arrays (doubles, 8-byte
+ * aligned, caller-owned); counts_dev: device counters, added to (zero them
+ * first).  Enqueued on hip_stream; AF_EINVAL for a bad kind, flag, size or
+ * pointer, AF_EHIP if the launch fails.  A verification aid, not a step of
+ * the method. */
+enum { AF_LIM_POINT = 0, AF_LIM_CENTRE = 1, AF_LIM_SOURCE = 2, AF_LIM_BOX = 3 };
+#define AF_LIM_NO_SHORTCUT 1u
+typedef struct {            /* device counters (the stage's own, in this order) */
+  int64_t n_llf_not_admissible, n_newton, newton_iters_max, n_fallback, n_not_admissible, n_theta_active,
+      n_point_limited, n_centre_limited, n_source_limited, min_theta_bits;
+} af_mhd_counters_t;
+int af_mhd_limiters_apply(int kind, int64_t n, double gamma, const double* in_dev, double* out_dev, uint32_t flags,
+                          af_mhd_counters_t* counts_dev, void* hip_stream);
 
 /* ------------------------------------------------------------ batches
  * A batch advances n independent grids together (each with its own

@@ -53,6 +53,7 @@ class af_mhd_stats_t(ctypes.Structure):
 
 AF_FLAG_FP32_BULK = 1
 AF_FLAG_KERNEL_TIMING = 4
+AF_FLAG_FUSED_DT = 8
 
 
 class af_mhd_kernel_times_t(ctypes.Structure):
@@ -117,6 +118,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.af_mhd_destroy.restype = None
     L.af_mhd_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.af_mhd_stream_copy.restype = ctypes.c_int
+    L.af_mhd_limiters_apply.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, vp, vp, ctypes.c_uint32, vp, vp]
+    L.af_mhd_limiters_apply.restype = ctypes.c_int
     L.af_mhd_adj_tape_bytes.argtypes = [P]
     L.af_mhd_adj_tape_bytes.restype = ctypes.c_size_t
     L.af_mhd_adj_workspace_bytes.argtypes = [P]
@@ -552,6 +555,34 @@ def stream_copy(src, dst, stream=None):
                                  ctypes.c_void_p(s.cuda_stream))
     if rc != AF_OK:
         raise AfMhdError(rc, "af_mhd_stream_copy failed")
+
+
+AF_LIM_POINT, AF_LIM_CENTRE, AF_LIM_SOURCE, AF_LIM_BOX = 0, 1, 2, 3
+AF_LIM_NO_SHORTCUT = 1
+_LIM_WIDTHS = {AF_LIM_POINT: (16, 8), AF_LIM_CENTRE: (16, 8), AF_LIM_SOURCE: (25, 9), AF_LIM_BOX: (42, 4)}
+COUNTER_NAMES = ("n_llf_not_admissible", "n_newton", "newton_iters_max", "n_fallback", "n_not_admissible",
+                 "n_theta_active", "n_point_limited", "n_centre_limited", "n_source_limited", "min_theta_bits")
+
+
+def af_mhd_limiters_apply(kind, inputs, gamma, flags=0, stream=None):
+    """The stage's limiter of the given kind on each row of inputs (a
+    float64 device tensor [n, width]); returns (outputs [n, width_out],
+    counters dict).  Synchronises."""
+    import torch
+
+    w_in, w_out = _LIM_WIDTHS[kind]
+    if inputs.dtype != torch.float64 or inputs.dim() != 2 or inputs.shape[1] != w_in or not inputs.is_contiguous():
+        raise ValueError("limiters_apply: contiguous float64 [n, %d] device tensor" % w_in)
+    out = torch.empty((inputs.shape[0], w_out), dtype=torch.float64, device=inputs.device)
+    cnt = torch.zeros(len(COUNTER_NAMES), dtype=torch.int64, device=inputs.device)
+    s = stream if stream is not None else torch.cuda.current_stream(inputs.device)
+    rc = _lib.af_mhd_limiters_apply(kind, inputs.shape[0], gamma, ctypes.c_void_p(inputs.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), flags, ctypes.c_void_p(cnt.data_ptr()),
+                                    ctypes.c_void_p(s.cuda_stream))
+    if rc != AF_OK:
+        raise AfMhdError(rc, "af_mhd_limiters_apply failed")
+    s.synchronize()
+    return out, dict(zip(COUNTER_NAMES, cnt.cpu().tolist()))
 
 
 def to_device(state, device="cuda"):

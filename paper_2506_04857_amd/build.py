@@ -6,7 +6,7 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("af_stage.hip", "af_batch.hip", "af_adjoint.hip", "af_util.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("af_stage.hip", "af_batch.hip", "af_adjoint.hip", "af_util.hip", "af_limiters.hip")]
 HEADERS = [os.path.join(PKG, "csrc", f) for f in ("af_device.h", "af_tiles.h", "af_adjoint.h", "af_adjoint_stage.h")] + [
     os.path.join(ROOT, "include", "af_mhd.h")]
 LIB = os.path.join(PKG, "libaf_mhd.so")

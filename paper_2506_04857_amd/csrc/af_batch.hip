@@ -140,11 +140,7 @@ __global__ __launch_bounds__(BLK) void kb_dt_partial(const BDt* __restrict__ D, 
       dof_ptr(g, u, t, base, plane, off);
       double U[NV];
       load8(base, plane, off, U);
-      DirEval e;
-      eval_dir(U, g, 0, e);
-      const double s1 = e.sr;
-      eval_dir(U, g, 1, e);
-      mx = fmax(mx, s1 * g.rdx + e.sr * g.rdy);
+      mx = fmax(mx, dt_speed(U, g));
     }
     mx = block_max(mx);
     if (threadIdx.x == 0) partial[it] = mx;

@@ -72,21 +72,31 @@ __device__ __forceinline__ void ldV(const Geo& g, const double* v, int k, int l,
 }
 
 // ------------------------------------------------------------------ physics
-// p = (gamma-1)(E - |m|^2/(2 rho) - |B|^2/2)
+// p = (gamma-1)(E - |m|^2/(2 rho) - |B|^2/2), summed left to right without
+// fused multiply-adds and with an IEEE division.  Every positivity limiter
+// takes its coefficients and its decisions (in G or not) from this form, so
+// that on identical inputs they are the reference's bit for bit: where the
+// variables' scales differ a lot these decisions are made by round-off.
 __device__ __forceinline__ double pressure(const double U[NV], double gm1) {
+#pragma clang fp contract(off)
   const double m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
   const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
   return gm1 * (U[7] - 0.5 * m2 / U[0] - 0.5 * b2);
 }
+// U in G: rho > 0 and p > 0 (Section 3), in the form above.
+__device__ __forceinline__ bool in_G(const double U[NV], double gm1) {
+  return U[0] > 0.0 && pressure(U, gm1) > 0.0;
+}
 // rho p / (gamma-1) = rho E - |m|^2/2 - rho |B|^2/2: for rho > 0 it has the
-// sign of p and p >= eps  <=>  (gamma-1) * this >= rho * eps.  Decisions use
-// this division-free form; pressures are computed only where a limiter acts.
+// sign of p and p >= eps  <=>  (gamma-1) * this >= rho * eps.  The fast
+// tests that no limiter needs to act, and the counters, use this
+// division-free form; a limiter that may act recomputes with pressure().
 __device__ __forceinline__ double rho_p(const double U[NV]) {
   const double m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
   const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
   return U[0] * (U[7] - 0.5 * b2) - 0.5 * m2;
 }
-__device__ __forceinline__ bool in_G(const double U[NV], double gm1) {
+__device__ __forceinline__ bool in_G_fast(const double U[NV]) {
   return U[0] > 0.0 && rho_p(U) > 0.0;
 }
 // p(U) >= eps for rho > 0
@@ -249,6 +259,7 @@ __device__ __forceinline__ void count_min_theta(Counters* cn, double t) {
 // 2^m 1e-8 (m = 0..9, each from the original value); 0 if none passes.
 template <class Make>
 __device__ double shrink_into_G(double theta, double gm1, Make make) {
+#pragma clang fp contract(off)
   double W[NV];
   for (int m = 0; m < 10; ++m) {
     const double t = fmax(theta - ldexp(SHRINK, m), 0.0);
@@ -262,6 +273,7 @@ __device__ double shrink_into_G(double theta, double gm1, Make make) {
 // whole-state blend towards the LLF state; eps from the LLF state.
 __device__ void limit_point(const double UH[NV], const double UL[NV], double gm1, double W[NV], Counters* cn,
                             bool counted) {
+#pragma clang fp contract(off)
   const double rhoL = UL[0];
   const double er = fmin(EPS_FLOOR, rhoL);
   // common case: the LLF state has p >= 1e-13 (so eps_p = 1e-13) and the
@@ -309,6 +321,7 @@ __device__ void limit_point(const double UH[NV], const double UL[NV], double gm1
 // for p >= eps_p, eps from the cell average.
 __device__ void limit_centre(const double Uc[NV], const double A[NV], double gm1, double C[NV], Counters* cn,
                              bool counted) {
+#pragma clang fp contract(off)
   const double rhoA = A[0];
   const double er = fmin(EPS_FLOOR, rhoA);
   if ((rhoA > 0.0) & p_at_least(A, EPS_FLOOR, gm1) & (Uc[0] >= er) & p_at_least(Uc, EPS_FLOOR, gm1)) {
@@ -345,10 +358,60 @@ __device__ void limit_centre(const double Uc[NV], const double A[NV], double gm1
   }
 }
 
+// Step (1) of the parametrized flux limiter (Section 3.2) for a cell whose
+// LLF-flux update is G: A^LLF = G - dt S^LLF, A^src = G - dt S^s (S^s the
+// sensor-blended high-order source); theta_src = 1 if p(A^src) >= eps_p,
+// otherwise the scaling fraction towards A^LLF; eps from A^LLF (R20).
+// A^{Lim,1} = theta A^src + (1 - theta) A^LLF, then the round-off fallback.
+// Returns theta_src; er, ep are the flux limiter's bounds.
+template <class R>
+__device__ double source_step(const double G[NV], const R S[NV], const R Sl[NV], double dt, double gm1,
+                              double A1[NV], double& er, double& ep, Counters* cn, bool counted) {
+#pragma clang fp contract(off)
+  double Allf[NV], Asrc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    Allf[c] = G[c] - dt * (double)Sl[c];
+    Asrc[c] = G[c] - dt * (double)S[c];
+  }
+  const double rhoL = Allf[0];
+  if (counted && !in_G_fast(Allf)) count(&cn->n_llf_not_admissible);
+  er = fmin(EPS_FLOOR, rhoL);
+  ep = EPS_FLOOR;
+  double th = 1.0;
+  if (!(rhoL > 0.0 && p_at_least(Allf, EPS_FLOOR, gm1) && p_at_least(Asrc, EPS_FLOOR, gm1))) {
+    // the step may act: the reference form of the pressures
+    const double pL = pressure(Allf, gm1);
+    ep = fmin(EPS_FLOOR, pL);
+    const double psrc = pressure(Asrc, gm1);
+    if (psrc < ep) {
+      th = (pL - ep) / (pL - psrc);
+      if (counted) count(&cn->n_source_limited);
+    }
+  }
+  auto make = [&](double tt, double* Wt) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Wt[c] = tt * Asrc[c] + (1.0 - tt) * Allf[c];
+  };
+  if (th == 1.0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) A1[c] = Asrc[c];
+  } else {
+    make(th, A1);
+  }
+  if (th > 0.0 && !in_G(A1, gm1)) {
+    if (counted) count(&cn->n_fallback);
+    th = shrink_into_G(th, gm1, make);
+    make(th, A1);
+  }
+  return th;
+}
+
 // The pressure condition along A1 + r D as the cubic of Section 3.2,
 // q(r) = rho (E - |B|^2/2 - eps_p/(gamma-1)) - |m|^2/2, and dq/dr.
 __device__ __forceinline__ void pressure_cubic(const double A1[NV], const double D[NV], double r, double gm1,
                                                double ep, double& q, double& dq) {
+#pragma clang fp contract(off)
   double W[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) W[c] = A1[c] + r * D[c];
@@ -362,6 +425,7 @@ __device__ __forceinline__ void pressure_cubic(const double A1[NV], const double
 
 // Root in (0,1) of the cubic by Newton from r = 1 inside a sign bracket.
 __device__ double vertex_root(const double A1[NV], const double D[NV], double gm1, double ep, int& iters) {
+#pragma clang fp contract(off)
   double lo = 0.0, hi = 1.0, r = 1.0;
   iters = 0;
   for (int it = 0; it < 50; ++it) {
@@ -382,9 +446,10 @@ __device__ double vertex_root(const double A1[NV], const double D[NV], double gm
 // pressure shrink over the 15 non-trivial vertices, Lambda_{L,R,D,U}, and
 // the round-off fallback on the final box.  H(I, c) returns component c of
 // the anti-diffusive update H_I (I = L, R, D, U).
-template <class HF>
+template <class HF, bool SHORTCUT = true>
 __device__ void limiter_box(const double A1[NV], HF H, double gm1, double er, double ep, double Lam[4], Counters* cn,
                             bool counted) {
+#pragma clang fp contract(off)
   double h0[4];
 #pragma unroll
   for (int I = 0; I < 4; ++I) h0[I] = H(I, 0);
@@ -396,10 +461,14 @@ __device__ void limiter_box(const double A1[NV], HF H, double gm1, double er, do
   for (int I = 0; I < 4; ++I) Lr[I] = h0[I] < 0.0 ? fmin(1.0, (A1[0] - er) / (LAMBDA_REG - neg)) : 1.0;
   // Sufficient test: every vertex A1 + sum_{I in K} Lr_I H_I is a convex
   // combination of A1 and the four points A1 + 4 Lr_I H_I (weights 1/4 and
-  // 1 - |K|/4), and {rho >= er, p >= ep} is convex; when those four points
-  // are admissible no vertex needs the pressure shrink.
-  {
-    bool all_ok = true;
+  // 1 - |K|/4), and {rho >= er, p >= ep} is convex; when A1 and those four
+  // points are admissible no vertex needs the pressure shrink.  A1 itself
+  // can miss ep: after the source step's round-off fallback it is only
+  // known to lie in G.  (Round-off aside the vertices then pass their own
+  // tests; where a vertex's pressure is within round-off of ep the per-vertex
+  // test may still ask for a root of size 1 - O(round-off).)
+  if constexpr (SHORTCUT) {
+    bool all_ok = A1[0] >= er && A1[0] > 0.0 && p_at_least(A1, ep, gm1);
 #pragma unroll
     for (int I = 0; I < 4; ++I) {
       double W[NV];

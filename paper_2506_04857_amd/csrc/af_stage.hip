@@ -34,28 +34,45 @@ struct WS {                 // workspace pointers
   Counters* cnt;
   double* scratch[2][4];    // two RK scratch states
   double* centre;           // limited centre values of the stage input, [8][ny][nx]
+  double* wpart;            // per-workgroup wave-speed maxima of a step's last stage
+  int nwpart;               // point-kernel grid + cell-kernel grid
 };
 
+inline int points_tiles_x(const Geo& g) { return (g.nxp + PB - 3) / (PB - 2); }
+inline int points_tiles_y(const Geo& g) { return (g.nyp + PB - 3) / (PB - 2); }
+inline int cells_tiles_x(const Geo& g) { return (g.nx + CBX0 - 4) / (CBX0 - 3); }
+inline int cells_tiles_y(const Geo& g) { return (g.ny + CBY0 - 4) / (CBY0 - 3); }
+
+// wpart: null, or one slot per workgroup for the maximum of rho_1/dx +
+// rho_2/dy over the values it stores (a step's last stage; padding
+// workgroups store 0).
 template <class R>
 __global__ __launch_bounds__(PNT, 2) void k_points(Geo g, CState u, CState un, MState out,
-                                                                         double* __restrict__ centre,
-                                                                         const double* dtp, double ca, double cb,
-                                                                         Counters* cn, int ntx, int nty) {
+                                                   double* __restrict__ centre, const double* dtp, double ca,
+                                                   double cb, Counters* cn, int ntx, int nty,
+                                                   double* __restrict__ wpart) {
   __shared__ R s[point_fields<R>()][PB][PB];
   int bx, by;
-  if (!xcd_tile(ntx, nty, bx, by)) return;
-  points_tile<R>(g, u, un, out, centre, *dtp, ca, cb, cn, bx, by, s);
+  if (!xcd_tile(ntx, nty, bx, by)) {
+    if (wpart && threadIdx.x == 0 && threadIdx.y == 0) wpart[blockIdx.x] = 0.0;
+    return;
+  }
+  points_tile<R>(g, u, un, out, centre, *dtp, ca, cb, cn, bx, by, s, wpart ? wpart + blockIdx.x : nullptr);
 }
 
 template <class R>
 __global__ __launch_bounds__(CBX0 * CBY0) void k_cells(Geo g, CState u, const double* __restrict__ centre,
                                                        const double* __restrict__ un, double* __restrict__ out,
                                                        const double* dtp, double ca, double cb, Counters* cn,
-                                                       int ntx, int nty) {
+                                                       int ntx, int nty, double* __restrict__ wpart) {
   __shared__ CellsLDS<R, CBX0, CBY0> L;
   int bx, by;
-  if (!xcd_tile(ntx, nty, bx, by)) return;
-  cells_tile<R, CBX0, CBY0>(g, u, centre, un, out, *dtp, ca, cb, cn, bx, by, L);
+  if (!xcd_tile(ntx, nty, bx, by)) {
+    if (wpart && threadIdx.x == 0 && threadIdx.y == 0) wpart[blockIdx.x] = 0.0;
+    return;
+  }
+  cells_tile<R, CBX0, CBY0>(g, u, centre, un, out, *dtp, ca, cb, cn, bx, by, L,
+                            wpart ? wpart + blockIdx.x : nullptr);
 }
 
 __global__ __launch_bounds__(BLK) void k_dt_partial(Geo g, CState u, double* partial) {
@@ -69,11 +86,7 @@ __global__ __launch_bounds__(BLK) void k_dt_partial(Geo g, CState u, double* par
     dof_ptr(g, u, t, base, plane, off);
     double U[NV];
     load8(base, plane, off, U);
-    DirEval e;
-    eval_dir(U, g, 0, e);
-    const double s1 = e.sr;
-    eval_dir(U, g, 1, e);
-    m = fmax(m, s1 * g.rdx + e.sr * g.rdy);
+    m = fmax(m, dt_speed(U, g));
   }
   m = block_max(m);
   if (threadIdx.x == 0) partial[blockIdx.x] = m;
@@ -83,6 +96,19 @@ __global__ __launch_bounds__(BLK) void k_dt_final(const double* partial, int npa
                                                   double* dt) {
   double m = 0.0;
   for (int t = threadIdx.x; t < nparts; t += BLK) m = fmax(m, partial[t]);
+  m = block_max(m);
+  if (threadIdx.x == 0) {
+    double d = cfl / m;
+    *dt = d > t_rem ? t_rem : d;
+  }
+}
+
+// dt from the per-workgroup maxima a step's last stage left (one workgroup).
+__global__ __launch_bounds__(BLK) void k_dt_from_parts(const double* wpart, int n, double cfl, double t_rem,
+                                                       double* dt) {
+  double m = 0.0;
+#pragma unroll 4
+  for (int t = threadIdx.x; t < n; t += BLK) m = fmax(m, wpart[t]);
   m = block_max(m);
   if (threadIdx.x == 0) {
     double d = cfl / m;
@@ -237,7 +263,11 @@ struct af_mhd_ctx {
   hipStream_t stream;
   std::string err;
   KernelTimer* timer = nullptr;
-  bool f32 = false;  // AF_FLAG_FP32_BULK
+  bool f32 = false;        // AF_FLAG_FP32_BULK
+  bool fused_dt = false;   // AF_FLAG_FUSED_DT
+  // the state whose wave-speed maxima ws.wpart holds (left by the last
+  // stage of af_mhd_step on it), or null
+  const double* wpart_for[4] = {nullptr, nullptr, nullptr, nullptr};
   ~af_mhd_ctx() {
     if (timer) {
       for (int q = 0; q < timer->created; ++q) (void)hipEventDestroy(timer->ev[q]);
@@ -258,7 +288,7 @@ bool valid_params(const af_mhd_params* p) {
   if ((p->bc_x != AF_BC_PERIODIC && p->bc_x != AF_BC_OUTFLOW) ||
       (p->bc_y != AF_BC_PERIODIC && p->bc_y != AF_BC_OUTFLOW))
     return false;
-  return (p->flags & ~(uint32_t)(AF_FLAG_KERNEL_TIMING | AF_FLAG_FP32_BULK)) == 0;
+  return (p->flags & ~(uint32_t)(AF_FLAG_KERNEL_TIMING | AF_FLAG_FP32_BULK | AF_FLAG_FUSED_DT)) == 0;
 }
 
 // Fold every recorded pair into the totals (synchronises on the last event).
@@ -330,6 +360,8 @@ size_t layout(const Geo& g, char* base, WS* ws) {
   for (int k = 0; k < 2; ++k)
     for (int q = 0; q < 4; ++q) w.scratch[k][q] = take(8 * sizes[q]);
   w.centre = take(8 * sizes[0]);
+  w.nwpart = xcd_grid(points_tiles_x(g), points_tiles_y(g)) + xcd_grid(cells_tiles_x(g), cells_tiles_y(g));
+  w.wpart = take((size_t)w.nwpart);
   if (ws) *ws = w;
   return off;
 }
@@ -360,8 +392,10 @@ bool valid_state(const af_mhd_state* s) {
 }
 CState cstate(const af_mhd_state* s) { return CState{s->cell, s->xface, s->yface, s->vert}; }
 
+// wpart: null, or the slots for the workgroups' wave-speed maxima of the
+// stage's outputs (point-kernel grid, then cell-kernel grid).
 int run_stage(af_mhd_ctx* c, int k, const af_mhd_state* un, const af_mhd_state* uk, af_mhd_state* out,
-              const double* dt_dev) {
+              const double* dt_dev, double* wpart = nullptr) {
   static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
   static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
   const Geo& g = c->g;
@@ -369,29 +403,45 @@ int run_stage(af_mhd_ctx* c, int k, const af_mhd_state* un, const af_mhd_state* 
   const CState u = cstate(uk);
   const CState n = cstate(k == 0 ? uk : un);  // not read when a_k = 0
   const MState o{out->cell, out->xface, out->yface, out->vert};
-  const int ptx = (g.nxp + PB - 3) / (PB - 2), pty = (g.nyp + PB - 3) / (PB - 2);
+  const int ptx = points_tiles_x(g), pty = points_tiles_y(g);
+  double* const wcells = wpart ? wpart + xcd_grid(ptx, pty) : nullptr;
   hipEvent_t end;
   hipError_t e = timer_begin(c, KernelTimer::POINTS, &end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   if (c->f32)
     k_points<float><<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(g, u, n, o, c->ws.centre, dt_dev, A[k], B[k],
-                                                                c->ws.cnt, ptx, pty);
+                                                                c->ws.cnt, ptx, pty, wpart);
   else
     k_points<double><<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(g, u, n, o, c->ws.centre, dt_dev, A[k], B[k],
-                                                                 c->ws.cnt, ptx, pty);
+                                                                 c->ws.cnt, ptx, pty, wpart);
   e = timer_end(c, end);
   if (e == hipSuccess) e = timer_begin(c, KernelTimer::CELLS, &end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
-  const int ctx_ = (g.nx + CBX0 - 4) / (CBX0 - 3), cty = (g.ny + CBY0 - 4) / (CBY0 - 3);
+  const int ctx_ = cells_tiles_x(g), cty = cells_tiles_y(g);
   if (c->f32)
     k_cells<float><<<xcd_grid(ctx_, cty), dim3(CBX0, CBY0), 0, s>>>(g, u, c->ws.centre, n.a, o.a, dt_dev, A[k], B[k],
-                                                                  c->ws.cnt, ctx_, cty);
+                                                                  c->ws.cnt, ctx_, cty, wcells);
   else
     k_cells<double><<<xcd_grid(ctx_, cty), dim3(CBX0, CBY0), 0, s>>>(g, u, c->ws.centre, n.a, o.a, dt_dev, A[k],
-                                                                   B[k], c->ws.cnt, ctx_, cty);
+                                                                   B[k], c->ws.cnt, ctx_, cty, wcells);
   e = timer_end(c, end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   return check_hip(c, "stage launch");
+}
+
+bool same_state(const double* const a[4], const af_mhd_state* u) {
+  return a[0] == u->cell && a[1] == u->xface && a[2] == u->yface && a[3] == u->vert;
+}
+
+// dt from the wave-speed maxima the last stage of the previous step left.
+int run_dt_from_parts(af_mhd_ctx* c, double t_rem, double* dt_dev) {
+  hipEvent_t end;
+  hipError_t e = timer_begin(c, KernelTimer::DT, &end);
+  if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
+  k_dt_from_parts<<<1, BLK, 0, c->stream>>>(c->ws.wpart, c->ws.nwpart, c->g.cfl, t_rem, dt_dev);
+  e = timer_end(c, end);
+  if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
+  return check_hip(c, "dt launch");
 }
 
 int run_dt(af_mhd_ctx* c, const af_mhd_state* u, double t_rem, double* dt_dev) {
@@ -437,6 +487,7 @@ int af_mhd_init(const af_mhd_params* p, void* workspace_dev, size_t workspace_by
   layout(c->g, static_cast<char*>(workspace_dev), &c->ws);
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->f32 = (p->flags & AF_FLAG_FP32_BULK) != 0;
+  c->fused_dt = (p->flags & AF_FLAG_FUSED_DT) != 0;
   if (p->flags & AF_FLAG_KERNEL_TIMING) {
     c->timer = new (std::nothrow) KernelTimer();
     if (!c->timer) {
@@ -469,6 +520,7 @@ int af_mhd_stage(af_mhd_ctx* c, int k, const af_mhd_state* un, const af_mhd_stat
     return fail(c, AF_EINVAL, "af_mhd_stage: bad argument");
   if (out->cell == uk->cell || out->xface == uk->xface || out->yface == uk->yface || out->vert == uk->vert)
     return fail(c, AF_EINVAL, "af_mhd_stage: out aliases uk");
+  for (auto& p : c->wpart_for) p = nullptr;  // the stage may write the state the maxima belong to
   return run_stage(c, k, un, uk, out, dt_dev);
 }
 
@@ -477,10 +529,18 @@ int af_mhd_step(af_mhd_ctx* c, af_mhd_state* u, double t_remaining, double* dt_d
   if (!valid_state(u) || !aligned8(dt_dev) || !(t_remaining > 0.0)) return fail(c, AF_EINVAL, "af_mhd_step: bad argument");
   af_mhd_state s1{c->ws.scratch[0][0], c->ws.scratch[0][1], c->ws.scratch[0][2], c->ws.scratch[0][3]};
   af_mhd_state s2{c->ws.scratch[1][0], c->ws.scratch[1][1], c->ws.scratch[1][2], c->ws.scratch[1][3]};
-  int rc = run_dt(c, u, t_remaining, dt_dev);
+  const bool reuse = c->fused_dt && same_state(c->wpart_for, u);
+  for (auto& p : c->wpart_for) p = nullptr;
+  int rc = reuse ? run_dt_from_parts(c, t_remaining, dt_dev) : run_dt(c, u, t_remaining, dt_dev);
   if (rc == AF_OK) rc = run_stage(c, 0, u, u, &s1, dt_dev);
   if (rc == AF_OK) rc = run_stage(c, 1, u, &s1, &s2, dt_dev);
-  if (rc == AF_OK) rc = run_stage(c, 2, u, &s2, u, dt_dev);
+  if (rc == AF_OK) rc = run_stage(c, 2, u, &s2, u, dt_dev, c->fused_dt ? c->ws.wpart : nullptr);
+  if (rc == AF_OK && c->fused_dt) {
+    c->wpart_for[0] = u->cell;
+    c->wpart_for[1] = u->xface;
+    c->wpart_for[2] = u->yface;
+    c->wpart_for[3] = u->vert;
+  }
   return rc;
 }
 

@@ -36,6 +36,39 @@ __device__ inline double sensor_pressure(const double U[NV], double gamma) {
   return (gamma - 1.0) * (U[7] - m2 / (2.0 * U[0]) - b2 / 2.0);
 }
 
+// rho_1/dx + rho_2/dy of a state (rho_l = |v_l| + c_f,l, eq. (cf)): dt is
+// cfl over its maximum over all DoFs.  Contraction-free, so that every
+// kernel that takes this maximum (the reduction over a state, the epilogue
+// of a step's last stage, the batched reduction) gets the same bits.
+__device__ __forceinline__ double dt_speed(const double U[NV], const Geo& g) {
+#pragma clang fp contract(off)
+  const double ri = rcp_r(U[0]);
+  const double v1 = U[1] * ri, v2 = U[2] * ri, v3 = U[3] * ri;
+  const double b2 = U[4] * U[4] + U[5] * U[5] + U[6] * U[6];
+  const double p = g.gm1 * (U[7] - 0.5 * (U[1] * v1 + U[2] * v2 + U[3] * v3) - 0.5 * b2);
+  const double c2 = g.gamma * p * ri;
+  const double s = c2 + b2 * ri;
+  double d1 = s * s - 4.0 * c2 * U[4] * U[4] * ri;
+  double d2 = s * s - 4.0 * c2 * U[5] * U[5] * ri;
+  d1 = d1 > 0.0 ? d1 : 0.0;
+  d2 = d2 > 0.0 ? d2 : 0.0;
+  const double c1 = sqrt_r(0.5 * (s + sqrt_r(d1))), cy = sqrt_r(0.5 * (s + sqrt_r(d2)));
+  return (fabs(v1) + c1) * g.rdx + (fabs(v2) + cy) * g.rdy;
+}
+
+// Maximum of v over the workgroup (nthreads a multiple of 64, every thread
+// calling), written by thread 0 to *slot.  scratch: nthreads/64 doubles of
+// LDS no other thread reads or writes meanwhile.
+__device__ __forceinline__ void block_max_store(double v, int tid, int nthreads, double* scratch, double* slot) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if ((tid & 63) == 0) scratch[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < nthreads / 64; ++w) v = fmax(v, scratch[w]);
+    *slot = v;
+  }
+}
+
 // ------------------------------------------------------- fused point update
 // One launch updates the point values V, X, Y owned by a tile of
 // (PB-2) x (PB-2) cells (cell (i,j) owns V(i,j), X(i,j), Y(i,j)); the
@@ -77,7 +110,7 @@ __device__ __forceinline__ void acc_zero(PointAcc<R>& P) {
 template <class R>
 __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[NV], const PointAcc<R>& P,
                                       double ca, double cb, const double* __restrict__ un, double* __restrict__ out,
-                                      long plane, long off, Counters* cn) {
+                                      long plane, long off, Counters* cn, double* wmax) {
   double UH[NV], UL[NV], W[NV];
   R Ps[NV];
   psi(U0, Ps);
@@ -94,16 +127,17 @@ __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[
       UL[c] = U0[c] + P.l[c] - dt * P.divl * Ps[c];
     }
   }
-  if (!in_G(UL, g.gm1)) count(&cn->n_llf_not_admissible);
+  if (!in_G_fast(UL)) count(&cn->n_llf_not_admissible);
   limit_point(UH, UL, g.gm1, W, cn, true);
   if (!in_G(W, g.gm1)) count(&cn->n_not_admissible);
-  if (ca == 0.0) {
+  if (ca != 0.0) {
 #pragma unroll
-    for (int c = 0; c < NV; ++c) out[c * plane + off] = W[c];
-  } else {
-#pragma unroll
-    for (int c = 0; c < NV; ++c) out[c * plane + off] = ca * un[c * plane + off] + cb * W[c];
+    for (int c = 0; c < NV; ++c) W[c] = ca * un[c * plane + off] + cb * W[c];
   }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) out[c * plane + off] = W[c];
+  // a step's last stage: the next step's wave-speed maximum over its outputs
+  if (wmax) *wmax = fmax(*wmax, dt_speed(W, g));
 }
 
 __device__ __forceinline__ int clamp_pt(int i, int np) { return i < -1 ? -1 : (i > np ? np : i); }
@@ -341,8 +375,11 @@ __device__ __forceinline__ void lean_fvs(R (*s)[PB][PB], int dir, int so, int sb
 template <class R>
 __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState un, MState out,
                                                  double* __restrict__ centre, double dt, double ca, double cb,
-                                                 Counters* cn, int bx, int by, R (*s)[PB][PB]) {
+                                                 Counters* cn, int bx, int by, R (*s)[PB][PB],
+                                                 double* __restrict__ wslot) {
   constexpr bool F32 = IsF32<R>::value;
+  double wm = 0.0;
+  double* const wmax = wslot ? &wm : nullptr;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i0 = bx * (PB - 2) - 1, j0 = by * (PB - 2) - 1;
   const int i = clamp_pt(i0 + tx, g.nxp), j = clamp_pt(j0 + ty, g.nyp);
@@ -467,7 +504,7 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
   lean_fvs<R, false>(s, 0, SX_, SC_, ty, tx, ty, txl, ty, txr, rdx, lxr, PX, PX);
   if (outX) {
     own(1, w);
-    finish(g, dt, w, PX, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn);
+    finish(g, dt, w, PX, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn, wmax);
   }
   pin_acc(PV);
   __syncthreads();
@@ -484,7 +521,7 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
   pin_acc(PY);
   if (outV) {
     own(0, w);
-    finish(g, dt, w, PV, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn);
+    finish(g, dt, w, PV, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn, wmax);
   }
   __syncthreads();
 
@@ -497,17 +534,24 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
   lean_fvs<R, false>(s, 1, SY_, SC_, ty, tx, tyd, tx, tyu, tx, rdy, lyr, PY, PY);
   if (outY) {
     own(2, w);
-    finish(g, dt, w, PY, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn);
+    finish(g, dt, w, PY, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn, wmax);
+  }
+  if (wslot) {
+    __syncthreads();  // the LDS is reused as the reduction's scratch
+    block_max_store(wm, ty * PB + tx, PNT, reinterpret_cast<double*>(&s[0][0][0]), wslot);
   }
 }
 
 // One tile of the point update (see above): FP64 stage (R = double) or
 // FP32-bulk stage (R = float).
+// wslot: null, or where the workgroup's maximum of rho_1/dx + rho_2/dy over
+// the values it stores goes (a step's last stage).
 template <class R>
 __device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, MState out,
                                             double* __restrict__ centre, double dt, double ca, double cb,
-                                            Counters* cn, int bx, int by, R (*s)[PB][PB]) {
-  points_tile_lean<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s);
+                                            Counters* cn, int bx, int by, R (*s)[PB][PB],
+                                            double* __restrict__ wslot = nullptr) {
+  points_tile_lean<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s, wslot);
 }
 
 // ------------------------------------------------------ fused cell update
@@ -687,7 +731,7 @@ template <class R, int CBX, int CBY>
 __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double* __restrict__ centre,
                                            const double* __restrict__ un, double* __restrict__ out, double dt,
                                            double ca, double cb, Counters* cn, int bx, int by,
-                                           CellsLDS<R, CBX, CBY>& L) {
+                                           CellsLDS<R, CBX, CBY>& L, double* __restrict__ wslot = nullptr) {
   constexpr int CNT = CBX * CBY;
   auto& s_dfx = L.dfx;
   auto& s_dfy = L.dfy;
@@ -840,7 +884,6 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
 
   // 4: LLF source, sensor blend of the source, flux-limiter steps (1)-(2)
   R Sl[NV];
-  double Allf[NV], Asrc[NV];
   {
     R P[NV];
     if constexpr (IsF32<R>::value) {
@@ -859,41 +902,10 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
     for (int c = 0; c < NV; ++c) {
       Sl[c] = (R)divb * P[c];
       S[c] = tsmin * S[c] + (R(1) - tsmin) * Sl[c];
-      Allf[c] = G[c] - dt * (double)Sl[c];
-      Asrc[c] = G[c] - dt * (double)S[c];
     }
   }
-  const double rhoL = Allf[0];
-  const bool llf_in = in_G(Allf, g.gm1);
-  if (output && !llf_in) count(&cn->n_llf_not_admissible);
-  const double er = fmin(EPS_FLOOR, rhoL);
-  double ep = EPS_FLOOR, th = 1.0;
-  double A1[NV];
-  if (!(rhoL > 0.0 && p_at_least(Allf, EPS_FLOOR, g.gm1) && p_at_least(Asrc, EPS_FLOOR, g.gm1))) {
-    // step (1) of the flux limiter may act: exact pressures
-    const double pL = pressure(Allf, g.gm1);
-    ep = fmin(EPS_FLOOR, pL);
-    const double psrc = pressure(Asrc, g.gm1);
-    if (psrc < ep) {
-      th = (pL - ep) / (pL - psrc);
-      if (output) count(&cn->n_source_limited);
-    }
-  }
-  auto make = [&](double tt, double* Wt) {
-#pragma unroll
-    for (int c = 0; c < NV; ++c) Wt[c] = tt * Asrc[c] + (1.0 - tt) * Allf[c];
-  };
-  if (th == 1.0) {
-#pragma unroll
-    for (int c = 0; c < NV; ++c) A1[c] = Asrc[c];
-  } else {
-    make(th, A1);
-  }
-  if (th > 0.0 && !in_G(A1, g.gm1)) {
-    if (output) count(&cn->n_fallback);
-    th = shrink_into_G(th, g.gm1, make);
-    make(th, A1);
-  }
+  double A1[NV], er, ep;
+  const double th = source_step(G, S, Sl, dt, g.gm1, A1, er, ep, cn, output);
   double SL[NV];  // S^Lim
 #pragma unroll
   for (int c = 0; c < NV; ++c) SL[c] = th * (double)S[c] + (1.0 - th) * (double)Sl[c];
@@ -903,7 +915,8 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
 #pragma unroll
   for (int I = 0; I < 4; ++I) s_lam[I][ty][tx] = Lam[I];
   __syncthreads();
-  if (!output) return;
+  double wm = 0.0;
+  if (output) {
   const double thL = fmin(s_lam[1][ty][tx - 1], Lam[0]);
   const double thR = fmin(Lam[1], s_lam[0][ty][tx + 1]);
   const double thD = fmin(s_lam[3][ty - 1][tx], Lam[2]);
@@ -918,12 +931,17 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
     An[c] = G[c] - dt * SL[c] + thL * H(0, c) + thR * H(1, c) + thD * H(2, c) + thU * H(3, c);
   if (!in_G(An, g.gm1)) count(&cn->n_not_admissible);
   const long off = (long)j * g.nx + i;
-  if (ca == 0.0) {
+  if (ca != 0.0) {
 #pragma unroll
-    for (int c = 0; c < NV; ++c) out[c * g.sc + off] = An[c];
-  } else {
+    for (int c = 0; c < NV; ++c) An[c] = ca * un[c * g.sc + off] + cb * An[c];
+  }
 #pragma unroll
-    for (int c = 0; c < NV; ++c) out[c * g.sc + off] = ca * un[c * g.sc + off] + cb * An[c];
+  for (int c = 0; c < NV; ++c) out[c * g.sc + off] = An[c];
+  if (wslot) wm = dt_speed(An, g);
+  }
+  if (wslot) {
+    __syncthreads();  // the Lambda exchange is read; its LDS is the scratch
+    block_max_store(wm, tid, CNT, reinterpret_cast<double*>(&L.ts[0][0][0]), wslot);
   }
 }
 

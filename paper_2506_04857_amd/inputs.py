@@ -308,6 +308,31 @@ def random_shock(n: int = 16, ny: int | None = None, seed: int = BASE_SEED, bc: 
     return Problem("random_shock", n, ny, 0.0, 1.0, 0.0, ny / n, 1.4, 0.2, 1.0, bc, bc, 1.0, prim)
 
 
+def low_beta_shock(n: int = 40, ny: int | None = None, seed: int = 3, b_mag: float = 1e4, p_in: float = 100.0,
+                   p_out: float = 1e-4, bc: int = OUTFLOW) -> Problem:
+    """Piecewise-constant data whose variables' scales differ a lot, as in
+    the paper's jets: a uniform field of strength b_mag (|B|^2/2 = 5e7 at
+    1e4) in a random direction, a disc of rho = 1, v = 0, p = p_in in a
+    moving ambient of rho = 0.1, p = p_out.  The pressure of a limited
+    state is then decided by the round-off of E - |m|^2/(2 rho) - |B|^2/2,
+    and the round-off fallback of the closing remark of Section 4 acts."""
+    rng = np.random.default_rng(seed)
+    ny = n if ny is None else ny
+    cx, cy = rng.uniform(0.35, 0.65, size=2)
+    r0 = rng.uniform(0.15, 0.3)
+    th = rng.uniform(0.0, 2.0 * math.pi)
+    b1, b2 = b_mag * math.cos(th), b_mag * math.sin(th)
+    v1, v2 = rng.uniform(-3.0, 3.0, size=2)
+
+    def prim(x, y, t):
+        ins = np.sqrt((x - cx) ** 2 + (y * n / ny - cy) ** 2) < r0
+        z = np.zeros_like(np.asarray(x, dtype=np.float64))
+        return _stack(np.where(ins, 1.0, 0.1), np.where(ins, 0.0, v1), np.where(ins, 0.0, v2), z, b1 + z, b2 + z, z,
+                      np.where(ins, p_in, p_out))
+
+    return Problem("low_beta_shock", n, ny, 0.0, 1.0, 0.0, ny / n, 1.4, 0.2, 1.0, bc, bc, 1.0, prim)
+
+
 def stirred(base: Problem, eps: float = 1e-2) -> Problem:
     """base with a small smooth velocity field added (eps sin / cos waves in
     v1 and v2): the shock sensor's phi2 = -div v / |(div v, curl v)| is then

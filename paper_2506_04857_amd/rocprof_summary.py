@@ -107,6 +107,13 @@ def main(argv=None):
             print(f"{k:<20} {w:>6.0f} {per['VALU']:>6.0f} {per['VALU_FMA_F64']:>6.0f} {per['VALU_ADD_F64']:>6.0f} "
                   f"{per['VALU_MUL_F64']:>6.0f} {per['VALU_TRANS_F64']:>7.0f} {per['LDS']:>5.0f} {per['SALU']:>5.0f} "
                   f"{100 * av.get(k, 0.0) / cyc:>6.1f}% {100 * al.get(k, 0.0) / cyc:>5.1f}% {conf.get(k, 0.0):>9.3g}")
+        # machine-readable: VALU wave-instructions per launch (bench.py reads these)
+        for k in sorted(waves):
+            if k.startswith("k_points") or k.startswith("k_cells") or k.startswith("k_dt"):
+                print(f"valu_insts_per_launch.{k}: {ins['VALU'].get(k, 0.0):.0f}")
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        from bench import source_hash
+        print(f"source_sha256: {source_hash()}")
         return
     if args.cmd == "kernels":
         print(f"{'kernel':<34} {'calls':>6} {'avg us':>10} {'min us':>10} {'max us':>10} {'share %':>8}")

@@ -58,12 +58,22 @@ def test_host_side_argument_checks(lib):
     for q in (replace(I.orszag_tang(64), gamma=1.0), replace(I.orszag_tang(64), cfl=0.0),
               replace(I.orszag_tang(64), kappa=-1.0), replace(I.orszag_tang(64), bc_x=7)):
         assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(q))) == 0
-    # flags: only the FP32-bulk and timing bits are accepted
-    from paper_2506_04857_amd.af_mhd import AF_FLAG_FP32_BULK, AF_FLAG_KERNEL_TIMING
+    # flags: only the FP32-bulk, timing and fused-dt bits are accepted
+    from paper_2506_04857_amd.af_mhd import AF_FLAG_FP32_BULK, AF_FLAG_FUSED_DT, AF_FLAG_KERNEL_TIMING
     assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), AF_FLAG_KERNEL_TIMING))) == n
     assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), AF_FLAG_FP32_BULK))) == n
+    assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), AF_FLAG_FUSED_DT))) == n
     assert L.af_mhd_workspace_bytes(ctypes.byref(make_params(I.orszag_tang(64), 1 << 7))) == 0
     assert L.af_mhd_kernel_times(None, None, 0) == AF_EINVAL
+    # the limiters entry: bad kind, flag or pointers are rejected on the host
+    L.af_mhd_limiters_apply.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    assert L.af_mhd_limiters_apply(4, 1, 1.4, 256, 256, 0, 256, None) == AF_EINVAL
+    assert L.af_mhd_limiters_apply(0, 1, 1.4, 256, 256, 2, 256, None) == AF_EINVAL
+    assert L.af_mhd_limiters_apply(0, 1, 1.0, 256, 256, 0, 256, None) == AF_EINVAL
+    assert L.af_mhd_limiters_apply(0, 1, 1.4, None, 256, 0, 256, None) == AF_EINVAL
+    assert L.af_mhd_limiters_apply(0, -1, 1.4, 256, 256, 0, 256, None) == AF_EINVAL
+    assert L.af_mhd_limiters_apply(0, 0, 1.4, None, None, 0, None, None) == 0
 
 
 def test_batch_host_side_argument_checks(lib):
@@ -102,13 +112,20 @@ def test_maximum_sizes(lib):
 
 
 def test_bench_traffic_is_tied_to_the_kernel_sources():
-    # bench.py reports the committed rocprofv3 traffic only for the kernel
-    # sources it was measured on (their SHA-256 is stored with it).
+    # bench.py reports the committed rocprofv3 traffic and VALU counts only
+    # for the kernel sources they were measured on (their SHA-256 is stored
+    # with them).
+    import os
     import bench
     h = bench.source_hash()
     assert h == bench.source_hash() and len(h) == 64
-    t = bench.measured_traffic("orszag_tang_512", "k_points")
-    with open(bench.TRAFFIC_FILE) as fh:
-        recorded = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("source_sha256")]
-    assert (t is not None) == (recorded == [h])
-    assert bench.measured_traffic("blast_lowbeta_1024", "k_points") is None
+    for wl, fname in bench.TRAFFIC_FILES.items():
+        path = os.path.join(bench.PROFILES, fname)
+        recorded = []
+        if os.path.exists(path):
+            with open(path) as fh:
+                recorded = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("source_sha256")]
+        t = bench.measured_traffic(wl, "k_points<double>")
+        assert (t is not None) == (recorded == [h])
+    assert bench.measured_traffic("alfven_32", "k_points<double>") is None
+    assert bench.measured_valu("alfven_32", "k_points<double>") is None

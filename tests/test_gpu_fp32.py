@@ -163,6 +163,37 @@ def test_fp32_blast_positivity_and_l1(af, oracle):
     assert l1_rho <= 1e-5 and l1_p <= 1e-4
 
 
+@pytest.mark.timeout(600)
+def test_fp32_blast_1024_against_the_fp64_oracle(af, oracle):
+    # The low-beta blast at its full size (1024^2, outflow, kappa = 1), 10
+    # steps with the oracle's dt sequence: min rho, min p and the L1 errors
+    # of rho and p of the FP32-bulk run against the FP64 oracle.
+    prob = I.blast_lowbeta(1024)
+    u0 = I.sample(prob)
+    ref, dts = u0, []
+    c = oracle.Counters()
+    say("[fp32] blast 1024: oracle 10 steps")
+    for _ in range(10):
+        ref, d = oracle.step(prob, ref, counters=c)
+        dts.append(d)
+    say("[fp32] blast 1024: fp32-bulk 10 steps")
+    got, st = fp32_run(af, prob, u0, 10, dts)
+    rho32, rho64 = got[0][0], ref[0][0]
+    p32, p64 = pressure(got[0], prob.gamma), pressure(ref[0], prob.gamma)
+    l1_rho = np.abs(rho32 - rho64).mean() / np.abs(rho64).mean()
+    l1_p = np.abs(p32 - p64).mean() / np.abs(p64).mean()
+    min_rho64 = min(a[0].min() for a in ref)
+    min_p64 = min(pressure(a, prob.gamma).min() for a in ref)
+    say(f"[fp32] blast 1024 x 10 steps: min rho {st['min_rho']:.6e} (fp64 oracle {min_rho64:.6e}), "
+        f"min p {st['min_p']:.6e} (fp64 oracle {min_p64:.6e}), L1 rel rho {l1_rho:.2e}, L1 rel p {l1_p:.2e}, "
+        f"points limited {st['n_point_limited']} (fp64 {c.n_point_limited}), "
+        f"centres limited {st['n_centre_limited']} (fp64 {c.n_centre_limited})")
+    assert st["admissible"] and st["n_not_admissible"] == 0
+    assert st["min_rho"] > 0 and st["min_p"] > 0
+    assert st["min_rho"] == pytest.approx(min_rho64, rel=1e-4)
+    assert l1_rho <= 1e-5 and l1_p <= 1e-4
+
+
 def test_fp32_differs_from_fp64_only_by_rounding(af):
     # The two precisions run the same scheme: on OT 128^2 after 10 steps
     # their difference is at the FP32 rounding level, far above FP64's.

@@ -98,6 +98,55 @@ def test_single_stages_match_oracle(af, oracle, name, make):
         assert_parity(got, ref, what=f"{name} k={k}")
 
 
+def ulp_perturbed(u, rng):
+    return tuple(a * (1 + rng.choice([-1.0, 1.0], size=a.shape) * 2.0 ** -52) for a in u)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("low_beta_shock_40x36_outflow", lambda: I.low_beta_shock(40, 36, seed=3, b_mag=300.0)),
+    ("low_beta_shock_37x33_periodic", lambda: I.low_beta_shock(37, 33, seed=3, b_mag=300.0, bc=I.PERIODIC)),
+])
+def test_round_off_fallback_stages_within_the_methods_own_sensitivity(af, oracle, name, make):
+    # Scales that differ a lot (|B|^2/2 = 4.5e4 against p down to 1e-4, the
+    # shock sensor off): the round-off fallback of the closing remark of
+    # Section 4 acts in both implementations.  Where it acts the stage is
+    # decided by round-off by definition: the oracle fed its own stage input
+    # perturbed by one ulp moves by 1e-10 .. 1e-8.  Every stage of three
+    # steps runs on the GPU from the oracle's stage inputs and must stay
+    # within that sensitivity: four times the largest move of the oracle
+    # over eight 1-ulp perturbations (the GPU's own rounding differences --
+    # fused multiply-adds, one-ulp reciprocals in the fluxes -- are a few
+    # ulps where they enter the limiters).  The limiter functions themselves
+    # are compared bit for bit on identical inputs in test_gpu_limiters.py.
+    prob = replace(make(), kappa=0.0)
+    u = I.sample(prob)
+    rng = np.random.default_rng(11)
+    fb_orc = fb_gpu = 0
+    for n in range(3):
+        dt = oracle.dt(prob, u)
+        uk = u
+        for k in range(3):
+            c = oracle.Counters()
+            ref = oracle.stage(prob, k, u, uk, dt, counters=c)
+            got, st = gpu_stage(af, prob, k, u, uk, dt)
+            sens = max(field_errors(oracle.stage(prob, k, ulp_perturbed(u, rng), ulp_perturbed(uk, rng), dt),
+                                    ref).max() for _ in range(8))
+            e = field_errors(got, ref).max()
+            say(f"[parity] {name} step {n} stage {k}: gpu vs oracle {e:.3e}, oracle 1-ulp sensitivity {sens:.3e}, "
+                f"fallback oracle {c.n_fallback} gpu {st['n_fallback']}")
+            assert e <= max(REL, 4.0 * sens), f"{name} step {n} k={k}"
+            # (at these scales round-off can also leave a final cell average
+            # just outside G, in either implementation: the fallback acts on
+            # the limiters' coefficients, not on the flux-form update)
+            say(f"[parity] {name} step {n} stage {k}: outputs outside G oracle {c.n_not_admissible} "
+                f"gpu {st['n_not_admissible']}")
+            fb_orc += c.n_fallback
+            fb_gpu += st["n_fallback"]
+            uk = ref
+        u = uk
+    assert fb_orc > 0 and fb_gpu > 0
+
+
 def gpu_run(af, prob, u0, nsteps, t_final=None):
     import torch
     ctx = af.Context(prob)
@@ -193,22 +242,46 @@ def test_orszag_tang_512_full_field_one_step(af, oracle):
     assert_parity(got, ref, what="orszag_tang_512")
 
 
+def neighbour(prob, a, di, dj):
+    """a at cell (i + di, j + dj): wrapped on a periodic axis, mirrored
+    about the boundary face on an outflow one (the oracle's ghost cells)."""
+    ny, nx = a.shape
+    ii = np.arange(nx) + di
+    jj = np.arange(ny) + dj
+    ii = np.where(ii < 0, -1 - ii, np.where(ii >= nx, 2 * nx - 1 - ii, ii)) if prob.bc_x else ii % nx
+    jj = np.where(jj < 0, -1 - jj, np.where(jj >= ny, 2 * ny - 1 - jj, jj)) if prob.bc_y else jj % ny
+    return a[np.ix_(jj, ii)]
+
+
 def ill_conditioned_sensor_cells(prob, A, rel=1e-9):
     """Cells whose discrete divergence d and curl w of the averaged velocity
     (the inputs of phi2 in Section 3.4) both vanish to within rounding:
     there phi2 = -d / sqrt(d^2 + w^2 + 1e-40) is decided by round-off."""
     v1, v2 = A[1] / A[0], A[2] / A[0]
-    sh = lambda a, di, dj: np.roll(np.roll(a, -di, axis=1), -dj, axis=0)
+    sh = lambda a, di, dj: neighbour(prob, a, di, dj)  # noqa: E731
     d = (sh(v1, 1, 0) - sh(v1, -1, 0)) / (2 * prob.dx) + (sh(v2, 0, 1) - sh(v2, 0, -1)) / (2 * prob.dy)
     w = (sh(v2, 1, 0) - sh(v2, -1, 0)) / (2 * prob.dx) - (sh(v1, 0, 1) - sh(v1, 0, -1)) / (2 * prob.dy)
     mag = np.sqrt(d * d + w * w)
     return mag <= rel * max(mag.max(), 1e-300)
 
 
-def dilate(mask, r):
+def dilate(mask, r, periodic_x=False, periodic_y=False):
+    """Cells within r steps (4-neighbourhood) of the mask; across a periodic
+    axis the neighbourhood wraps, across an outflow axis it does not."""
     out = mask.copy()
     for _ in range(r):
-        out = out | np.roll(out, 1, 0) | np.roll(out, -1, 0) | np.roll(out, 1, 1) | np.roll(out, -1, 1)
+        n = out.copy()
+        if periodic_y:
+            n |= np.roll(out, 1, 0) | np.roll(out, -1, 0)
+        else:
+            n[1:] |= out[:-1]
+            n[:-1] |= out[1:]
+        if periodic_x:
+            n |= np.roll(out, 1, 1) | np.roll(out, -1, 1)
+        else:
+            n[:, 1:] |= out[:, :-1]
+            n[:, :-1] |= out[:, 1:]
+        out = n
     return out
 
 
@@ -238,7 +311,7 @@ def test_blast_1024_full_field(af, oracle):
         # phi2 matters only where phi1 does not vanish (theta^s depends on phi1 * phi2)
         phi1 = oracle.cell_diagnostics(prob, u)[2][:2].max(axis=0)
         bad |= ill_conditioned_sensor_cells(prob, u[0]) & (phi1 > 1e-13)
-    far = ~dilate(bad, 12)
+    far = ~dilate(bad, 12, periodic_x=prob.bc_x == I.PERIODIC, periodic_y=prob.bc_y == I.PERIODIC)
     ref = ins[3]
     e = 0.0
     for c in range(8):
@@ -247,7 +320,9 @@ def test_blast_1024_full_field(af, oracle):
             e = max(e, np.abs(got[0][c] - ref[0][c])[far].max() / scale)
     say(f"[parity] blast_lowbeta_1024 one step: {bad.sum()} ill-conditioned cells, "
         f"{far.mean():.3f} of the cells compared, worst rel err {e:.3e}")
-    assert far.mean() > 0.5
+    # measured with the oracle alone: 1888 ill-conditioned cells, 0.985 of
+    # the cells outside their radius-12 neighbourhood
+    assert far.mean() >= 0.98
     assert e <= REL
 
 
@@ -365,3 +440,46 @@ def test_solver_runs_to_the_final_time(af, oracle):
         tr += d
     assert tr == pytest.approx(0.05, rel=1e-14)
     assert_parity(got, ref, what="solver run")
+
+
+@pytest.mark.parametrize("name,make", [
+    ("blast_lowbeta_96_outflow", lambda: I.blast_lowbeta(96)),
+    ("orszag_tang_70x37", lambda: I.orszag_tang(70).with_size(70, 37)),
+    ("smooth_13x9_periodic_fp32", lambda: I.random_smooth(13, 9, seed=1)),
+])
+def test_fused_dt_equals_the_full_reduction(af, oracle, name, make):
+    # AF_FLAG_FUSED_DT: each step's dt comes from the wave-speed maxima the
+    # previous step's last stage left; it must be bitwise the dt of the full
+    # reduction over the same state, and the steps bitwise those of a
+    # context without the flag.  A stage call in between falls back to the
+    # full reduction.
+    import torch
+    prob = make()
+    extra = af.AF_FLAG_FP32_BULK if name.endswith("fp32") else 0
+    u0 = I.sample(prob)
+    fused = af.Context(prob, flags=af.AF_FLAG_FUSED_DT | extra)
+    plain = af.Context(prob, flags=extra)
+    uf, up = af.to_device(u0), af.to_device(u0)
+    probe = af.Context(prob, flags=extra)
+    for n in range(6):
+        probe.af_mhd_dt(uf, 1.0)
+        want = float(probe.dt_dev.item())
+        fused.af_mhd_step(uf, 1.0)
+        plain.af_mhd_step(up, 1.0)
+        got = float(fused.dt_dev.item())
+        assert got == want == float(plain.dt_dev.item()), (n, got, want)
+        if n == 0:
+            assert got == pytest.approx(oracle.dt(prob, u0), rel=1e-13)
+        if n == 3:
+            # a stage on another state through the fused context: invalidates
+            scratch = af.empty_state(prob)
+            fused.af_mhd_stage(0, uf, uf, scratch)
+    # the final time is honoured from the fused maxima too
+    fused.af_mhd_step(uf, 1e-9)
+    plain.af_mhd_step(up, 1e-9)
+    assert float(fused.dt_dev.item()) == 1e-9
+    torch.cuda.synchronize()
+    for a, b in zip(af.to_host(uf), af.to_host(up)):
+        assert np.array_equal(a, b)
+    for c in (fused, plain, probe):
+        c.close()

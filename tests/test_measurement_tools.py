@@ -74,6 +74,9 @@ def test_sq_summary_per_wave_counts_and_busy_fraction(tmp_path):
     row = [ln for ln in txt.splitlines() if ln.startswith("k_points<double>")][0].split()
     assert row[1] == "100" and row[2] == "3000"  # waves, VALU per wave
     assert row[9] == "50.0%" and row[10] == "10.0%"  # 128000 / 256 / 1000, 25600 / 256 / 1000
+    kv = dict(ln.split(": ", 1) for ln in txt.splitlines() if ": " in ln)
+    assert float(kv["valu_insts_per_launch.k_points<double>"]) == 300000.0  # what bench.py reads
+    assert len(kv["source_sha256"]) == 64
 
 
 def test_bench_algorithmic_bytes_per_cell():
