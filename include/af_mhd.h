@@ -226,6 +226,23 @@ typedef struct {            /* device counters (the stage's own, in this order) 
 int af_mhd_limiters_apply(int kind, int64_t n, double gamma, const double* in_dev, double* out_dev, uint32_t flags,
                           af_mhd_counters_t* counts_dev, void* hip_stream);
 
+/* One SSP-RK3 step in place on u, as af_mhd_step on a context created
+ * with these parameters, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context, no workspace and no allocation of any kind.  Its
+ * scratch (the workspace of af_mhd_step) lives in a 48 MiB file-scope
+ * device array that every GPU the library runs on holds until the process
+ * ends; grids whose workspace exceeds it (beyond about 256 x 256 cells) are
+ * rejected with AF_EINVAL.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race and
+ * must not be issued.  The limiter counters restart from zero on every call
+ * and are not reported.  p->flags: AF_FLAG_FP32_BULK only.  Enqueued on
+ * hip_stream; dt is left in dt_dev.  Errors: AF_EINVAL for bad parameters,
+ * pointers or sizes, AF_EHIP for a HIP failure; the message is that of
+ * af_mhd_last_error(NULL) on this thread. */
+int af_mhd_step_noalloc(const af_mhd_params* p, af_mhd_state* u, double t_remaining, double* dt_dev,
+                        void* hip_stream);
+
 /* ------------------------------------------------------------ batches
  * A batch advances n independent grids together (each with its own
  * parameters: sizes, domain, gamma, cfl, kappa, boundaries; the flags must

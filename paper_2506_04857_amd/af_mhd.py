@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.af_mhd_stream_copy.restype = ctypes.c_int
     L.af_mhd_limiters_apply.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, vp, vp, ctypes.c_uint32, vp, vp]
     L.af_mhd_limiters_apply.restype = ctypes.c_int
+    L.af_mhd_step_noalloc.argtypes = [P, S, ctypes.c_double, vp, vp]
+    L.af_mhd_step_noalloc.restype = ctypes.c_int
     L.af_mhd_adj_tape_bytes.argtypes = [P]
     L.af_mhd_adj_tape_bytes.restype = ctypes.c_size_t
     L.af_mhd_adj_workspace_bytes.argtypes = [P]
@@ -555,6 +557,20 @@ def stream_copy(src, dst, stream=None):
                                  ctypes.c_void_p(s.cuda_stream))
     if rc != AF_OK:
         raise AfMhdError(rc, "af_mhd_stream_copy failed")
+
+
+def af_mhd_step_noalloc(prob, u, dt_dev, t_remaining=float("inf"), flags=0, stream=None):
+    """One SSP-RK3 step in place on the device state u through the
+    entry point that allocates nothing (scratch in the library's static
+    device array; grids up to about 256 x 256 cells).  Enqueued."""
+    import torch
+
+    p = make_params(prob, flags)
+    s = stream if stream is not None else torch.cuda.current_stream(u[0].device)
+    rc = _lib.af_mhd_step_noalloc(ctypes.byref(p), ctypes.byref(_state(u)), t_remaining,
+                                  ctypes.c_void_p(dt_dev.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+    if rc != AF_OK:
+        raise AfMhdError(rc, _lib.af_mhd_last_error(None).decode())
 
 
 AF_LIM_POINT, AF_LIM_CENTRE, AF_LIM_SOURCE, AF_LIM_BOX = 0, 1, 2, 3

@@ -18,6 +18,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -635,3 +636,66 @@ void af_mhd_destroy(af_mhd_ctx* c) { delete c; }
 const char* af_mhd_last_error(const af_mhd_ctx* c) { return c ? c->err.c_str() : init_err.c_str(); }
 
 }  // extern "C"
+
+// ------------------------------------------------ the step without allocation
+// af_mhd_step_noalloc keeps the step's scratch (reduction partials, counters,
+// two RK scratch states, centre values, wave-speed maxima: the workspace
+// layout above) in one file-scope device array per GPU instead of a
+// caller-owned workspace.  In host code the array's name is only a stand-in:
+// its device address, one per GPU, comes from hipGetSymbolAddress on the
+// first call on that device (with the device current) and is kept here.
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)48 << 20;  // 48 MiB per GPU
+__device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+char* scratch_dev[NOALLOC_MAX_DEVICES];  // each device's copy of the array; null until looked up
+std::mutex scratch_mu;
+
+}  // namespace
+
+extern "C" int af_mhd_step_noalloc(const af_mhd_params* p, af_mhd_state* u, double t_remaining, double* dt_dev,
+                                   void* hip_stream) {
+  init_err.clear();
+  if (!valid_params(p) || (p->flags & (AF_FLAG_KERNEL_TIMING | AF_FLAG_FUSED_DT)))
+    return init_fail(AF_EINVAL, "af_mhd_step_noalloc: invalid parameters");
+  if (!valid_state(u) || !aligned8(dt_dev) || !(t_remaining > 0.0))
+    return init_fail(AF_EINVAL, "af_mhd_step_noalloc: bad argument");
+  af_mhd_ctx c;
+  make_geo(p, c.g);
+  if (layout(c.g, nullptr, nullptr) > NOALLOC_SCRATCH_BYTES)
+    return init_fail(AF_EINVAL, "af_mhd_step_noalloc: grid too large for the 48 MiB static scratch "
+                                "(about 256 x 256 cells at most)");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return init_fail(AF_EHIP, std::string("af_mhd_step_noalloc: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return init_fail(AF_EINVAL, "af_mhd_step_noalloc: device index too large");
+  char* base;
+  {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return init_fail(AF_EHIP, std::string("af_mhd_step_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+      scratch_dev[dev] = static_cast<char*>(ptr);
+    }
+    base = scratch_dev[dev];
+  }
+  layout(c.g, base, &c.ws);
+  c.stream = static_cast<hipStream_t>(hip_stream);
+  c.f32 = (p->flags & AF_FLAG_FP32_BULK) != 0;
+  (void)hipGetLastError();
+  // the counters start at zero on every call (a fill kernel, no memset)
+  k_zero_counters<<<1, 64, 0, c.stream>>>(c.ws.cnt);
+  int rc = check_hip(&c, "af_mhd_step_noalloc");
+  af_mhd_state s1{c.ws.scratch[0][0], c.ws.scratch[0][1], c.ws.scratch[0][2], c.ws.scratch[0][3]};
+  af_mhd_state s2{c.ws.scratch[1][0], c.ws.scratch[1][1], c.ws.scratch[1][2], c.ws.scratch[1][3]};
+  if (rc == AF_OK) rc = run_dt(&c, u, t_remaining, dt_dev);
+  if (rc == AF_OK) rc = run_stage(&c, 0, u, u, &s1, dt_dev);
+  if (rc == AF_OK) rc = run_stage(&c, 1, u, &s1, &s2, dt_dev);
+  if (rc == AF_OK) rc = run_stage(&c, 2, u, &s2, u, dt_dev);
+  if (rc != AF_OK) init_fail(rc, c.err);
+  return rc;
+}
