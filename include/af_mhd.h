@@ -246,17 +246,18 @@ int af_mhd_step_noalloc(const af_mhd_params* p, af_mhd_state* u, double t_remain
 /* ------------------------------------------------------------ batches
  * A batch advances n independent grids together (each with its own
  * parameters: sizes, domain, gamma, cfl, kappa, boundaries; the flags must
- * agree).  Per SSP-RK3 step it runs one persistent launch computing every
- * instance's dt (min(cfl / max wave speed, t_remaining)), then per stage
- * one persistent launch of the point update over the (instance, tile) work
- * items of all instances and one of the cell update per cell-tile shape in
- * use; the step can be captured once into a hipGraph and replayed.  Each
+ * agree).  Per SSP-RK3 step it runs one launch computing every instance's
+ * dt (min(cfl / max wave speed, t_remaining)), then per stage one launch of
+ * the point update over the (instance, tile) work items of all instances and
+ * one launch of the cell update over theirs (32 x 16 or 16 x 32 cell tiles:
+ * the shape tuned for the size classes holding most of the batch's cells);
+ * the step can be captured once into a hipGraph and replayed.  Each
  * instance's results are bitwise equal to what a single-grid context
  * computes on it. */
 typedef struct af_mhd_batch af_mhd_batch;
 
 /* Bytes of device workspace for n instances with parameters p[0..n-1]
- * (two RK scratch states and a centre buffer per instance, dt partials,
+ * (two RK scratch states and a nine-point source buffer per instance, dt partials,
  * counters, launch tables).  0 for invalid parameters or mixed flags. */
 size_t af_mhd_batch_workspace_bytes(const af_mhd_params* p, int n);
 
@@ -279,7 +280,8 @@ int af_mhd_batch_init(const af_mhd_params* p, int n, const af_mhd_state* states,
  * call launches the graph; 0: plain launches. */
 int af_mhd_batch_step(af_mhd_batch* b, int use_graph);
 
-/* Cell-tile shape (threads in x and y) used for instance m. */
+/* Cell-tile shape (threads in x and y) of the batch's cell launch, which
+ * instance m runs on (the same for every m). */
 int af_mhd_batch_tile(const af_mhd_batch* b, int m, int* tile_x, int* tile_y);
 
 /* Launch mode of the stage kernels: 1 persistent (about one resident wave

@@ -404,14 +404,21 @@ class CheckpointedRun:
     """n SSP-RK3 steps of one grid with the gradient of their end state by
     the discrete adjoint and sqrt(n) checkpointing.
 
-    forward(): the fast stage kernels advance the state, keep the state every
-    `every` steps (default ceil(sqrt(n))) and the dt of every step in device
-    memory.  backward(lam): for each segment, last first, the recording
-    stage recomputes the segment from its checkpoint (keeping its stage
-    inputs and tapes, 3 per step), then the reverse sweep runs its steps
-    backwards.  The dt sequence is data (frozen), not differentiated."""
+    forward(): the recording stage advances the state (its tape is not
+    kept), keeping the state every `every` steps (default ceil(sqrt(n))) and
+    the dt of every step in device memory.  backward(lam): for each segment,
+    last first, the recording stage recomputes the segment from its
+    checkpoint (keeping its stage inputs and tapes, 3 per step), then the
+    reverse sweep runs its steps backwards.  The recording stage is
+    deterministic, so the recomputation takes exactly the forward's
+    decisions and reproduces its states bit for bit: the gradient is that of
+    the trajectory forward() returned.  With record_forward=False the fast
+    stage kernels advance the forward instead (equal to the recording stage
+    only to rounding, so the decisions the backward freezes are those of a
+    trajectory within rounding of the returned one).  The dt sequence is data
+    (frozen), not differentiated."""
 
-    def __init__(self, prob, device=None, every: int | None = None):
+    def __init__(self, prob, device=None, every: int | None = None, record_forward: bool = True):
         import torch
 
         self.prob = prob
@@ -419,8 +426,10 @@ class CheckpointedRun:
         self.ctx = Context(prob, device=self.device)
         self.adj = Adjoint(prob, device=self.device, stream=self.ctx.stream)
         self.every = every
+        self.record_forward = record_forward
         self.dts = None
         self.checkpoints = []
+        self.recomputed_end = None
 
     def _zeros(self):
         import torch
@@ -451,8 +460,10 @@ class CheckpointedRun:
         return out
 
     def forward(self, u0, nsteps: int, dts=None, t_final: float = float("inf")):
-        """Returns the end state (new tensors).  dts: a device tensor of fixed
-        step sizes to use instead of the CFL rule."""
+        """Returns the end state (new tensors) after nsteps steps, or fewer
+        when t_final is reached first (each step's dt is capped by the time
+        remaining; self.nsteps holds the steps taken).  dts: a device tensor
+        of fixed step sizes to use instead of the CFL rule."""
         import math
 
         import torch
@@ -468,18 +479,34 @@ class CheckpointedRun:
         else:
             self.dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=self.device)
         s1, s2 = self._zeros(), self._zeros()
+        s3 = self._zeros() if self.record_forward else None
+        tape = self.adj.new_tape() if self.record_forward else None
         t = 0.0
         for s in range(nsteps):
+            if math.isfinite(t_final) and t >= t_final:
+                self.nsteps = s  # t_final reached: the run ends here
+                break
             if s % every == 0:
                 self.checkpoints.append(tuple(x.clone() for x in u))
-            if dts is None:
-                self.ctx.af_mhd_step(u, t_final - t if math.isfinite(t_final) else float("inf"))
-                self.dts[s:s + 1].copy_(self.ctx.dt_dev)
+            rem = t_final - t if math.isfinite(t_final) else float("inf")
+            d = self.dts[s:s + 1]
+            if self.record_forward:
+                if dts is None:
+                    self.ctx.af_mhd_dt(u, rem)
+                    d.copy_(self.ctx.dt_dev)
+                self.adj.record(0, u, u, s1, d, tape)
+                self.adj.record(1, u, s1, s2, d, tape)
+                self.adj.record(2, u, s2, s3, d, tape)
+                u, s3 = s3, u
+            elif dts is None:
+                self.ctx.af_mhd_step(u, rem)
+                d.copy_(self.ctx.dt_dev)
             else:
-                d = self.dts[s:s + 1]
                 self.ctx.af_mhd_stage(0, u, u, s1, d)
                 self.ctx.af_mhd_stage(1, u, s1, s2, d)
                 self.ctx.af_mhd_stage(2, u, s2, u, d)
+            if math.isfinite(t_final):
+                t += float(d.item())  # the time reached (one synchronisation per step)
         return u
 
     def backward(self, lam_T):
@@ -502,6 +529,8 @@ class CheckpointedRun:
                 self.adj.record(2, u, u2, u3, d, t2)
                 hist.append((u, u1, u2, t0, t1, t2, d))
                 u = u3
+            if c == len(self.checkpoints) - 1:
+                self.recomputed_end = u  # the recomputed end state (equal to forward's)
             for un, u1, u2, t0, t1, t2, d in reversed(hist):
                 # the sweep adds into its accumulators
                 ln, l2, l1 = self._zero_states(3)

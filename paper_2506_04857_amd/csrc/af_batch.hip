@@ -1,11 +1,12 @@
 // af_batch.hip -- batched ensembles: many independent grids, of any sizes,
-// advanced together.  Per SSP-RK3 step: one persistent launch for the dt of
-// every instance (plus its per-instance finish), then per stage one
-// persistent launch of the point update over the (instance, tile) work items
-// of all instances and one of the cell update per cell-tile shape in use.
-// The step is captured once into a hipGraph and replayed.  The cell-tile
-// shape of each grid size is chosen by measurement (autotune) and kept in a
-// text table that later runs reuse.
+// advanced together.  Per SSP-RK3 step: one launch for the dt of every
+// instance (plus its per-instance finish), then per stage one launch of the
+// point update over the (instance, tile) work items of all instances and one
+// launch of the cell update over theirs (32 x 16 or 16 x 32 tiles: the
+// shape tuned for most of the batch's cells); persistent workgroups or one
+// item per workgroup, whichever is faster on the batch.  The step is captured once into a
+// hipGraph and replayed.  The cell-tile shape of each grid size is chosen
+// by measurement (autotune) and kept in a text table that later runs reuse.
 //
 // Each instance computes exactly what a single-grid context computes on it
 // (same arithmetic per DoF; max reductions are order-independent), so its
@@ -29,16 +30,16 @@ using namespace afm;
 namespace {
 
 // Cell-tile shapes the autotuner chooses from (threads = cells + ring).
-constexpr int NSHAPE = 3;
-const int SHAPE_X[NSHAPE] = {32, 16, 16};
-const int SHAPE_Y[NSHAPE] = {16, 32, 16};
+constexpr int NSHAPE = 2;
+const int SHAPE_X[NSHAPE] = {32, 16};
+const int SHAPE_Y[NSHAPE] = {16, 32};
 
 struct BInst {          // one instance in one launch of one stage
   Geo g;
   CState u;             // stage input U^(k)
   CState un;            // U^n (read when a_k != 0)
   MState out;           // stage output
-  double* centre;       // limited centre values of U^(k)
+  double* src;          // nine-point sources of U^(k)'s cells
   const double* dt;     // the instance's time step (device)
   int first;            // first work item of the instance in this launch
   int ntx;              // tiles per row in this launch
@@ -101,10 +102,12 @@ __global__ __launch_bounds__(PNT, 2) void kb_points(const BInst* __restrict__ I,
     const Geo g = I[m].g;
     const int t = it - I[m].first, ntx = I[m].ntx;
     __syncthreads();  // the previous item's LDS reads are done
-    points_tile<R>(g, I[m].u, I[m].un, I[m].out, I[m].centre, *I[m].dt, ca, cb, cn, t % ntx, t / ntx, s);
+    points_tile<R>(g, I[m].u, I[m].un, I[m].out, I[m].src, *I[m].dt, ca, cb, cn, t % ntx, t / ntx, s);
   }
 }
 
+// The cell update of every instance in one launch, on CBX x CBY tiles
+// (the batch's tuned shape).
 template <class R, int CBX, int CBY, bool PERSIST>
 __global__ __launch_bounds__(CBX * CBY) void kb_cells(const BInst* __restrict__ I, int n, int items, double ca,
                                                       double cb, Counters* cn) {
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(CBX * CBY) void kb_cells(const BInst* __restrict__ 
     const Geo g = I[m].g;
     const int t = it - I[m].first, ntx = I[m].ntx;
     __syncthreads();
-    cells_tile<R, CBX, CBY>(g, I[m].u, I[m].centre, I[m].un.a, I[m].out.a, *I[m].dt, ca, cb, cn, t % ntx,
+    cells_tile<R, CBX, CBY>(g, I[m].u, I[m].src, I[m].un.a, I[m].out.a, *I[m].dt, ca, cb, cn, t % ntx,
                             t / ntx, L);
   }
 }
@@ -174,11 +177,8 @@ template <class R, bool P>
 void launch_cells_m(int shape, int grid, hipStream_t s, const BInst* I, int n, int items, double ca, double cb,
                     Counters* cn) {
   const int g = P ? grid : flat_grid(items);
-  switch (shape) {
-    case 0: kb_cells<R, 32, 16, P><<<g, dim3(32, 16), 0, s>>>(I, n, items, ca, cb, cn); break;
-    case 1: kb_cells<R, 16, 32, P><<<g, dim3(16, 32), 0, s>>>(I, n, items, ca, cb, cn); break;
-    default: kb_cells<R, 16, 16, P><<<g, dim3(16, 16), 0, s>>>(I, n, items, ca, cb, cn); break;
-  }
+  if (shape == 0) kb_cells<R, 32, 16, P><<<g, dim3(32, 16), 0, s>>>(I, n, items, ca, cb, cn);
+  else kb_cells<R, 16, 32, P><<<g, dim3(16, 32), 0, s>>>(I, n, items, ca, cb, cn);
 }
 template <class R>
 void launch_cells(bool persist, int shape, int grid, hipStream_t s, const BInst* I, int n, int items, double ca,
@@ -195,11 +195,8 @@ void launch_points(bool persist, int grid, hipStream_t s, const BInst* I, int n,
 
 template <class R>
 const void* cells_fn(int shape) {
-  switch (shape) {
-    case 0: return reinterpret_cast<const void*>(&kb_cells<R, 32, 16, true>);
-    case 1: return reinterpret_cast<const void*>(&kb_cells<R, 16, 32, true>);
-    default: return reinterpret_cast<const void*>(&kb_cells<R, 16, 16, true>);
-  }
+  return shape == 0 ? reinterpret_cast<const void*>(&kb_cells<R, 32, 16, true>)
+                    : reinterpret_cast<const void*>(&kb_cells<R, 16, 32, true>);
 }
 
 int cell_tiles_x(const Geo& g, int shape) { return (g.nx + SHAPE_X[shape] - 4) / (SHAPE_X[shape] - 3); }
@@ -218,22 +215,22 @@ struct af_mhd_batch {
   std::vector<Geo> geo;
   std::vector<af_mhd_state> user;       // the bound states
   std::vector<af_mhd_state> s1, s2;     // RK scratch per instance
-  std::vector<double*> centre;
-  std::vector<int> shape;               // cell-tile shape per instance
+  std::vector<double*> src;             // nine-point source buffer per instance
+  std::vector<int> shape;               // tuned cell-tile shape of each instance's size class
+  int cshape = 0;                       // the shape of the batch's one cell launch
   double* dt = nullptr;                 // caller's dt array
   const double* t_rem = nullptr;        // caller's t_remaining array or null
   // device tables
   BInst* pts[3] = {nullptr, nullptr, nullptr};
-  BInst* cls[3][NSHAPE] = {};
+  BInst* cls[3] = {nullptr, nullptr, nullptr};  // every instance, grouped by shape
   int pts_items = 0;
-  int cls_items[NSHAPE] = {0, 0, 0};
-  int cls_n[NSHAPE] = {0, 0, 0};
+  int cls_items = 0;
   BDt* dts = nullptr;
   BInst* tune = nullptr;                // TUNE_COPIES entries for the autotuner
   int dt_items = 0;
   double* partial = nullptr;
   Counters* cnt = nullptr;
-  int grid_points = 0, grid_cells[NSHAPE] = {0, 0, 0}, grid_dt = 0;
+  int grid_points = 0, grid_cells = 0, grid_dt = 0;
   bool persist = false;                 // persistent or flat stage launches
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -284,7 +281,7 @@ size_t state_doubles(const Geo& g) { return 8 * (size_t)(g.sc + g.sx + g.sy + g.
 
 int dt_parts(const Geo& g) { return (int)((g.sc + g.sx + g.sy + g.sv + DT_CHUNK - 1) / DT_CHUNK); }
 
-// Device workspace: per instance two scratch states and a centre buffer,
+// Device workspace: per instance two scratch states and a nine-point source buffer,
 // then the dt partials, the counters and the launch tables.
 size_t batch_layout(const af_mhd_params* p, int n, char* base, af_mhd_batch* b) {
   size_t off = 0;
@@ -305,12 +302,12 @@ size_t batch_layout(const af_mhd_params* p, int n, char* base, af_mhd_batch* b) 
       if (b) (k ? b->s2 : b->s1).push_back(af_mhd_state{a, x, y, v});
     }
     double* c = reinterpret_cast<double*>(take(8 * sizeof(double) * g.sc));
-    if (b) b->centre.push_back(c);
+    if (b) b->src.push_back(c);
     parts += dt_parts(g);
   }
   double* partial = reinterpret_cast<double*>(take(sizeof(double) * parts));
   Counters* cnt = reinterpret_cast<Counters*>(take(sizeof(Counters)));
-  char* tabs = take(sizeof(BInst) * (size_t)n * 3 * (1 + NSHAPE) + sizeof(BDt) * (size_t)n);
+  char* tabs = take(sizeof(BInst) * (size_t)n * 3 * 2 + sizeof(BDt) * (size_t)n);
   char* tune = take(sizeof(BInst) * (size_t)TUNE_COPIES);
   if (b) {
     b->partial = partial;
@@ -319,10 +316,8 @@ size_t batch_layout(const af_mhd_params* p, int n, char* base, af_mhd_batch* b) 
     for (int k = 0; k < 3; ++k) {
       b->pts[k] = t;
       t += n;
-      for (int q = 0; q < NSHAPE; ++q) {
-        b->cls[k][q] = t;
-        t += n;
-      }
+      b->cls[k] = t;
+      t += n;
     }
     b->dts = reinterpret_cast<BDt*>(t);
     b->tune = reinterpret_cast<BInst*>(tune);
@@ -354,11 +349,12 @@ int persistent_grid(const void* fn, int threads) {
 // Fill the launch tables of every stage for the current shapes.
 int build_tables(af_mhd_batch* b) {
   const int n = b->n;
-  std::vector<BInst> pts(n), cls[NSHAPE];
+  std::vector<BInst> pts(n), cls;
   std::vector<BDt> dts(n);
   for (int k = 0; k < 3; ++k) {
-    int pfirst = 0, cfirst[NSHAPE] = {0, 0, 0};
-    for (int q = 0; q < NSHAPE; ++q) cls[q].clear();
+    int pfirst = 0, cfirst = 0;
+    cls.clear();
+    const int q = b->cshape;
     for (int m = 0; m < n; ++m) {
       const Geo& g = b->geo[m];
       const af_mhd_state& U = b->user[m];
@@ -369,27 +365,37 @@ int build_tables(af_mhd_batch* b) {
       r.u = CState{in.cell, in.xface, in.yface, in.vert};
       r.un = CState{U.cell, U.xface, U.yface, U.vert};
       r.out = MState{out.cell, out.xface, out.yface, out.vert};
-      r.centre = b->centre[m];
+      r.src = b->src[m];
+      r.dt = b->dt + m;
+      r.first = cfirst;
+      r.ntx = cell_tiles_x(g, q);
+      cls.push_back(r);
+      cfirst += cell_tiles_x(g, q) * cell_tiles_y(g, q);
+    }
+    for (int m = 0; m < n; ++m) {
+      const Geo& g = b->geo[m];
+      const af_mhd_state& U = b->user[m];
+      const af_mhd_state& in = k == 0 ? U : (k == 1 ? b->s1[m] : b->s2[m]);
+      const af_mhd_state& out = k == 0 ? b->s1[m] : (k == 1 ? b->s2[m] : U);
+      BInst r;
+      r.g = g;
+      r.u = CState{in.cell, in.xface, in.yface, in.vert};
+      r.un = CState{U.cell, U.xface, U.yface, U.vert};
+      r.out = MState{out.cell, out.xface, out.yface, out.vert};
+      r.src = b->src[m];
       r.dt = b->dt + m;
       r.first = pfirst;
       r.ntx = point_tiles_x(g);
       pts[m] = r;
       pfirst += point_tiles_x(g) * point_tiles_y(g);
-      const int q = b->shape[m];
-      r.first = cfirst[q];
-      r.ntx = cell_tiles_x(g, q);
-      cls[q].push_back(r);
-      cfirst[q] += cell_tiles_x(g, q) * cell_tiles_y(g, q);
     }
     b->pts_items = pfirst;
+    b->cls_items = cfirst;
     hipError_t e = hipMemcpyAsync(b->pts[k], pts.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, b->stream);
-    for (int q = 0; q < NSHAPE && e == hipSuccess; ++q) {
-      b->cls_items[q] = cfirst[q];
-      b->cls_n[q] = (int)cls[q].size();
-      if (!cls[q].empty())
-        e = hipMemcpyAsync(b->cls[k][q], cls[q].data(), sizeof(BInst) * cls[q].size(), hipMemcpyHostToDevice,
-                           b->stream);
-    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->cls[k], cls.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, b->stream);
+    // the host vectors are reused for the next stage: the copies must be done
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bcheck(b, e, "batch tables");
   }
   int first = 0;
@@ -421,15 +427,12 @@ int enqueue_step(af_mhd_batch* b) {
       launch_points<float>(b->persist, b->grid_points, s, b->pts[k], b->n, b->pts_items, A[k], B[k], b->cnt);
     else
       launch_points<double>(b->persist, b->grid_points, s, b->pts[k], b->n, b->pts_items, A[k], B[k], b->cnt);
-    for (int q = 0; q < NSHAPE; ++q) {
-      if (b->cls_n[q] == 0) continue;
-      if (b->f32)
-        launch_cells<float>(b->persist, q, b->grid_cells[q], s, b->cls[k][q], b->cls_n[q], b->cls_items[q], A[k],
-                            B[k], b->cnt);
-      else
-        launch_cells<double>(b->persist, q, b->grid_cells[q], s, b->cls[k][q], b->cls_n[q], b->cls_items[q], A[k],
-                             B[k], b->cnt);
-    }
+    if (b->f32)
+      launch_cells<float>(b->persist, b->cshape, b->grid_cells, s, b->cls[k], b->n, b->cls_items, A[k], B[k],
+                          b->cnt);
+    else
+      launch_cells<double>(b->persist, b->cshape, b->grid_cells, s, b->cls[k], b->n, b->cls_items, A[k], B[k],
+                           b->cnt);
   }
   return bcheck(b, hipSuccess, "batch step launch");
 }
@@ -465,7 +468,7 @@ std::map<std::string, int> read_table(const char* path) {
 // items repeated until a launch carries about TUNE_ITEMS of them (a filled
 // device, as in a batch), computing stage 0 into the instance's scratch
 // state (the copies write identical values); the point update runs first so
-// that the centre buffer is valid.  Returns the fastest shape; us[] gets
+// that the source buffer is valid.  Returns the fastest shape; us[] gets
 // the time per instance-launch of each shape.
 int tune_instance(af_mhd_batch* b, int m, double us[NSHAPE]) {
   const Geo& g = b->geo[m];
@@ -475,7 +478,7 @@ int tune_instance(af_mhd_batch* b, int m, double us[NSHAPE]) {
   r.u = CState{U.cell, U.xface, U.yface, U.vert};
   r.un = r.u;
   r.out = MState{b->s1[m].cell, b->s1[m].xface, b->s1[m].yface, b->s1[m].vert};
-  r.centre = b->centre[m];
+  r.src = b->src[m];
   r.dt = b->dt + m;
   hipStream_t s = b->stream;
   // a valid dt for the instances first
@@ -544,15 +547,10 @@ double time_stage0(af_mhd_batch* b, int reps) {
     kb_dt_final<<<b->n, BLK, 0, s>>>(b->dts, b->partial, b->t_rem, b->dt);
     if (b->f32) launch_points<float>(b->persist, b->grid_points, s, b->pts[0], b->n, b->pts_items, A0, B0, b->cnt);
     else launch_points<double>(b->persist, b->grid_points, s, b->pts[0], b->n, b->pts_items, A0, B0, b->cnt);
-    for (int q = 0; q < NSHAPE; ++q) {
-      if (b->cls_n[q] == 0) continue;
-      if (b->f32)
-        launch_cells<float>(b->persist, q, b->grid_cells[q], s, b->cls[0][q], b->cls_n[q], b->cls_items[q], A0, B0,
-                            b->cnt);
-      else
-        launch_cells<double>(b->persist, q, b->grid_cells[q], s, b->cls[0][q], b->cls_n[q], b->cls_items[q], A0,
-                             B0, b->cnt);
-    }
+    if (b->f32)
+      launch_cells<float>(b->persist, b->cshape, b->grid_cells, s, b->cls[0], b->n, b->cls_items, A0, B0, b->cnt);
+    else
+      launch_cells<double>(b->persist, b->cshape, b->grid_cells, s, b->cls[0], b->n, b->cls_items, A0, B0, b->cnt);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -610,8 +608,7 @@ int af_mhd_batch_init(const af_mhd_params* p, int n, const af_mhd_state* states,
   batch_layout(p, n, static_cast<char*>(workspace_dev), b);
   b->grid_points = b->f32 ? persistent_grid(reinterpret_cast<const void*>(&kb_points<float, true>), PNT)
                           : persistent_grid(reinterpret_cast<const void*>(&kb_points<double, true>), PNT);
-  for (int q = 0; q < NSHAPE; ++q)
-    b->grid_cells[q] = persistent_grid(b->f32 ? cells_fn<float>(q) : cells_fn<double>(q), SHAPE_X[q] * SHAPE_Y[q]);
+  b->grid_cells = persistent_grid(b->f32 ? cells_fn<float>(0) : cells_fn<double>(0), 512);  // 512 threads either shape
   b->grid_dt = persistent_grid(reinterpret_cast<const void*>(&kb_dt_partial), BLK);
   (void)hipGetLastError();
   kb_zero_counters<<<1, 64, 0, b->stream>>>(b->cnt);
@@ -648,7 +645,13 @@ int af_mhd_batch_init(const af_mhd_params* p, int n, const af_mhd_state* states,
         std::fclose(f);
       }
     }
-    if (rc == AF_OK) rc = build_tables(b);
+    if (rc == AF_OK) {
+      // the batch's one cell launch takes the shape tuned for most of its cells
+      long cells[NSHAPE] = {0, 0};
+      for (int m = 0; m < n; ++m) cells[b->shape[m]] += (long)b->geo[m].nx * b->geo[m].ny;
+      b->cshape = cells[1] > cells[0] ? 1 : 0;
+      rc = build_tables(b);
+    }
     if (rc == AF_OK) {
       // launch mode of the whole batch: persistent or one item per workgroup
       b->persist = true;
@@ -688,8 +691,8 @@ int af_mhd_batch_step(af_mhd_batch* b, int use_graph) {
 
 int af_mhd_batch_tile(const af_mhd_batch* b, int m, int* tile_x, int* tile_y) {
   if (!b || m < 0 || m >= b->n || !tile_x || !tile_y) return AF_EINVAL;
-  *tile_x = SHAPE_X[b->shape[m]];
-  *tile_y = SHAPE_Y[b->shape[m]];
+  *tile_x = SHAPE_X[b->cshape];
+  *tile_y = SHAPE_Y[b->cshape];
   return AF_OK;
 }
 

@@ -113,9 +113,12 @@ template <class R> struct IsF32 { static constexpr bool value = false; };
 template <> struct IsF32<float> { static constexpr bool value = true; };
 
 // Reciprocal and square root of the flux evaluations and the LLF viscosity.
-// FP64: the hardware approximations refined by two Newton steps (about one
-// ulp instead of correctly rounded, with much shorter dependency chains);
-// arguments are positive or zero (sqrt(0) = 0), never denormal in practice.
+// FP64: the hardware approximations (relative error up to 2^-23) refined by
+// Newton steps -- two for the reciprocal; one for the reciprocal square
+// root, then one correction of sqrt(x) = x / sqrt(x) itself, which squares
+// the remaining ~2e-14 (about one ulp instead of correctly rounded, with
+// much shorter dependency chains than the library sequences); arguments are
+// positive or zero (sqrt(0) = 0), never denormal in practice.
 // FP32: the hardware's one-ulp instructions.  Pressures, the sensor, the
 // limiters and their roots use exact division and sqrt.
 template <class R> __device__ __forceinline__ R rcp_r(R x);
@@ -129,7 +132,6 @@ template <class R> __device__ __forceinline__ R sqrt_r(R x);
 template <> __device__ __forceinline__ double sqrt_r<double>(double x) {
   double r = __builtin_amdgcn_rsq(x);  // 1/sqrt(x)
   const double h = 0.5 * x;
-  r = r * fma(-h * r, r, 1.5);
   r = r * fma(-h * r, r, 1.5);
   double q = x * r;                    // sqrt(x), then one correction
   q = fma(fma(-q, q, x), 0.5 * r, q);
@@ -219,8 +221,8 @@ __device__ __forceinline__ void flux_dir(const double U[NV], double gm1, int dir
 }
 
 // Godunov-Powell vector Psi = (0, B, v, v.B), eq. (gp_src).
-template <class R>
-__device__ __forceinline__ void psi(const double U[NV], R P[NV]) {
+template <class R, class S>
+__device__ __forceinline__ void psi(const S U[NV], R P[NV]) {
   const R ri = rcp_r((R)U[0]);
   const R v1 = (R)U[1] * ri, v2 = (R)U[2] * ri, v3 = (R)U[3] * ri;
   P[0] = R(0);
@@ -378,9 +380,15 @@ __device__ double source_step(const double G[NV], const R S[NV], const R Sl[NV],
   if (counted && !in_G_fast(Allf)) count(&cn->n_llf_not_admissible);
   er = fmin(EPS_FLOOR, rhoL);
   ep = EPS_FLOOR;
+  if (rhoL > 0.0 && p_at_least(Allf, EPS_FLOOR, gm1) && p_at_least(Asrc, EPS_FLOOR, gm1)) {
+    // both bounds hold with eps_p = 1e-13: theta_src = 1, A^{Lim,1} in G
+#pragma unroll
+    for (int c = 0; c < NV; ++c) A1[c] = Asrc[c];
+    return 1.0;
+  }
+  // the step may act: the reference form of the pressures
   double th = 1.0;
-  if (!(rhoL > 0.0 && p_at_least(Allf, EPS_FLOOR, gm1) && p_at_least(Asrc, EPS_FLOOR, gm1))) {
-    // the step may act: the reference form of the pressures
+  {
     const double pL = pressure(Allf, gm1);
     ep = fmin(EPS_FLOOR, pL);
     const double psrc = pressure(Asrc, gm1);

@@ -7,13 +7,14 @@
 //   k_points  point values (Section 2.3): centre values (Section 2.1,
 //             remark rmk:cell_center), LLF flux-vector splitting with the
 //             central div B source, first-order LLF safe state and scaling
-//             limiter (Section 3.3), SSP combination
+//             limiter (Section 3.3), SSP combination; and each cell's
+//             nine-point Powell source (Section 2.2) from the tile's points
 //   k_cells   cell averages (Sections 2.2, 3.1-3.4): Simpson and LLF fluxes,
-//             shock sensor, nine-point and LLF Powell sources, parametrized
-//             flux limiter, limited update in flux form, SSP combination
+//             shock sensor, LLF Powell source, parametrized flux limiter,
+//             limited update in flux form, SSP combination
 // Both are LDS-tiled: a tile's states and the costly per-point quantities
 // are computed once and shared through LDS, cheap ones (fluxes) rebuilt
-// where they are used; only the centre values pass through HBM.
+// where they are used; only the nine-point sources pass through HBM.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -34,7 +35,7 @@ struct WS {                 // workspace pointers
   double* partial;          // reduction partials
   Counters* cnt;
   double* scratch[2][4];    // two RK scratch states
-  double* centre;           // limited centre values of the stage input, [8][ny][nx]
+  double* src;              // nine-point sources of the stage input's cells, [8][ny][nx]
   double* wpart;            // per-workgroup wave-speed maxima of a step's last stage
   int nwpart;               // point-kernel grid + cell-kernel grid
 };
@@ -47,33 +48,33 @@ inline int cells_tiles_y(const Geo& g) { return (g.ny + CBY0 - 4) / (CBY0 - 3); 
 // wpart: null, or one slot per workgroup for the maximum of rho_1/dx +
 // rho_2/dy over the values it stores (a step's last stage; padding
 // workgroups store 0).
-template <class R>
+// WDT: a step's last stage, whose epilogue also writes the wave-speed maxima.
+template <class R, bool WDT>
 __global__ __launch_bounds__(PNT, 2) void k_points(Geo g, CState u, CState un, MState out,
-                                                   double* __restrict__ centre, const double* dtp, double ca,
+                                                   double* __restrict__ src, const double* dtp, double ca,
                                                    double cb, Counters* cn, int ntx, int nty,
                                                    double* __restrict__ wpart) {
   __shared__ R s[point_fields<R>()][PB][PB];
   int bx, by;
   if (!xcd_tile(ntx, nty, bx, by)) {
-    if (wpart && threadIdx.x == 0 && threadIdx.y == 0) wpart[blockIdx.x] = 0.0;
+    if (WDT && threadIdx.x == 0 && threadIdx.y == 0) wpart[blockIdx.x] = 0.0;
     return;
   }
-  points_tile<R>(g, u, un, out, centre, *dtp, ca, cb, cn, bx, by, s, wpart ? wpart + blockIdx.x : nullptr);
+  points_tile<R>(g, u, un, out, src, *dtp, ca, cb, cn, bx, by, s, WDT ? wpart + blockIdx.x : nullptr);
 }
 
-template <class R>
-__global__ __launch_bounds__(CBX0 * CBY0) void k_cells(Geo g, CState u, const double* __restrict__ centre,
+template <class R, bool WDT>
+__global__ __launch_bounds__(CBX0 * CBY0) void k_cells(Geo g, CState u, const double* __restrict__ src,
                                                        const double* __restrict__ un, double* __restrict__ out,
                                                        const double* dtp, double ca, double cb, Counters* cn,
                                                        int ntx, int nty, double* __restrict__ wpart) {
   __shared__ CellsLDS<R, CBX0, CBY0> L;
   int bx, by;
   if (!xcd_tile(ntx, nty, bx, by)) {
-    if (wpart && threadIdx.x == 0 && threadIdx.y == 0) wpart[blockIdx.x] = 0.0;
+    if (WDT && threadIdx.x == 0 && threadIdx.y == 0) wpart[blockIdx.x] = 0.0;
     return;
   }
-  cells_tile<R, CBX0, CBY0>(g, u, centre, un, out, *dtp, ca, cb, cn, bx, by, L,
-                            wpart ? wpart + blockIdx.x : nullptr);
+  cells_tile<R, CBX0, CBY0>(g, u, src, un, out, *dtp, ca, cb, cn, bx, by, L, WDT ? wpart + blockIdx.x : nullptr);
 }
 
 __global__ __launch_bounds__(BLK) void k_dt_partial(Geo g, CState u, double* partial) {
@@ -360,7 +361,7 @@ size_t layout(const Geo& g, char* base, WS* ws) {
   const size_t sizes[4] = {(size_t)g.sc, (size_t)g.sx, (size_t)g.sy, (size_t)g.sv};
   for (int k = 0; k < 2; ++k)
     for (int q = 0; q < 4; ++q) w.scratch[k][q] = take(8 * sizes[q]);
-  w.centre = take(8 * sizes[0]);
+  w.src = take(8 * sizes[0]);
   w.nwpart = xcd_grid(points_tiles_x(g), points_tiles_y(g)) + xcd_grid(cells_tiles_x(g), cells_tiles_y(g));
   w.wpart = take((size_t)w.nwpart);
   if (ws) *ws = w;
@@ -409,22 +410,24 @@ int run_stage(af_mhd_ctx* c, int k, const af_mhd_state* un, const af_mhd_state* 
   hipEvent_t end;
   hipError_t e = timer_begin(c, KernelTimer::POINTS, &end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
-  if (c->f32)
-    k_points<float><<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(g, u, n, o, c->ws.centre, dt_dev, A[k], B[k],
-                                                                c->ws.cnt, ptx, pty, wpart);
-  else
-    k_points<double><<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(g, u, n, o, c->ws.centre, dt_dev, A[k], B[k],
-                                                                 c->ws.cnt, ptx, pty, wpart);
+  {
+    if (c->f32)
+      (wpart ? k_points<float, true> : k_points<float, false>)<<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(
+          g, u, n, o, c->ws.src, dt_dev, A[k], B[k], c->ws.cnt, ptx, pty, wpart);
+    else
+      (wpart ? k_points<double, true> : k_points<double, false>)<<<xcd_grid(ptx, pty), dim3(PB, PB), 0, s>>>(
+          g, u, n, o, c->ws.src, dt_dev, A[k], B[k], c->ws.cnt, ptx, pty, wpart);
+  }
   e = timer_end(c, end);
   if (e == hipSuccess) e = timer_begin(c, KernelTimer::CELLS, &end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   const int ctx_ = cells_tiles_x(g), cty = cells_tiles_y(g);
   if (c->f32)
-    k_cells<float><<<xcd_grid(ctx_, cty), dim3(CBX0, CBY0), 0, s>>>(g, u, c->ws.centre, n.a, o.a, dt_dev, A[k], B[k],
-                                                                  c->ws.cnt, ctx_, cty, wcells);
+    (wcells ? k_cells<float, true> : k_cells<float, false>)<<<xcd_grid(ctx_, cty), dim3(CBX0, CBY0), 0, s>>>(
+        g, u, c->ws.src, n.a, o.a, dt_dev, A[k], B[k], c->ws.cnt, ctx_, cty, wcells);
   else
-    k_cells<double><<<xcd_grid(ctx_, cty), dim3(CBX0, CBY0), 0, s>>>(g, u, c->ws.centre, n.a, o.a, dt_dev, A[k],
-                                                                   B[k], c->ws.cnt, ctx_, cty, wcells);
+    (wcells ? k_cells<double, true> : k_cells<double, false>)<<<xcd_grid(ctx_, cty), dim3(CBX0, CBY0), 0, s>>>(
+        g, u, c->ws.src, n.a, o.a, dt_dev, A[k], B[k], c->ws.cnt, ctx_, cty, wcells);
   e = timer_end(c, end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   return check_hip(c, "stage launch");
@@ -639,7 +642,7 @@ const char* af_mhd_last_error(const af_mhd_ctx* c) { return c ? c->err.c_str() :
 
 // ------------------------------------------------ the step without allocation
 // af_mhd_step_noalloc keeps the step's scratch (reduction partials, counters,
-// two RK scratch states, centre values, wave-speed maxima: the workspace
+// two RK scratch states, nine-point sources, wave-speed maxima: the workspace
 // layout above) in one file-scope device array per GPU instead of a
 // caller-owned workspace.  In host code the array's name is only a stand-in:
 // its device address, one per GPU, comes from hipGetSymbolAddress on the

@@ -69,6 +69,51 @@ __device__ __forceinline__ void block_max_store(double v, int tid, int nthreads,
   }
 }
 
+// Nine-point Powell source of a cell, eq. (semi_av_src): weights
+// (1/6, 2/3, 1/6) per direction, the divergence at each sample point from
+// the one-sided / central differences of eq. (2d_fd) along the cell's rows
+// and columns, Psi at each point.  Bat(a, b, B1, B2) and Psiat(a, b, P) give
+// the field and Psi at sample (a, b) (a along x, b along y; (1, 1) is the
+// limited centre value): one body of arithmetic whichever memory the
+// samples come from.
+template <class R, class BF, class PF>
+__device__ __forceinline__ void source_nine(BF Bat, PF Psiat, R rdx, R rdy, R S[NV]) {
+  R B1[3][3], B2[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Bat(a, b, B1[a][b], B2[a][b]);
+  const R wq[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+  R f[9];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R dx1 = a == 0 ? (R(-3) * B1[0][b] + R(4) * B1[1][b] - B1[2][b])
+                  : a == 1 ? (B1[2][b] - B1[0][b])
+                           : (B1[0][b] - R(4) * B1[1][b] + R(3) * B1[2][b]);
+      const R dy2 = b == 0 ? (R(-3) * B2[a][0] + R(4) * B2[a][1] - B2[a][2])
+                  : b == 1 ? (B2[a][2] - B2[a][0])
+                           : (B2[a][0] - R(4) * B2[a][1] + R(3) * B2[a][2]);
+      f[3 * b + a] = wq[a] * wq[b] * (dx1 * rdx + dy2 * rdy);
+    }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) S[c] = R(0);
+  // Three samples per trip: their loads are in flight together, while the
+  // states of all nine are never live together.
+#pragma unroll 3
+  for (int q = 0; q < 9; ++q) {
+    const int a = q % 3, b = q / 3;
+    R fq = f[0];
+#pragma unroll
+    for (int r = 1; r < 9; ++r) fq = q == r ? f[r] : fq;
+    R P[NV];
+    Psiat(a, b, P);
+#pragma unroll
+    for (int c = 1; c < NV; ++c) S[c] += fq * P[c];
+  }
+}
+
 // ------------------------------------------------------- fused point update
 // One launch updates the point values V, X, Y owned by a tile of
 // (PB-2) x (PB-2) cells (cell (i,j) owns V(i,j), X(i,j), Y(i,j)); the
@@ -129,7 +174,7 @@ __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[
   }
   if (!in_G_fast(UL)) count(&cn->n_llf_not_admissible);
   limit_point(UH, UL, g.gm1, W, cn, true);
-  if (!in_G(W, g.gm1)) count(&cn->n_not_admissible);
+  if (!in_G_fast(W)) count(&cn->n_not_admissible);
   if (ca != 0.0) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) W[c] = ca * un[c * plane + off] + cb * W[c];
@@ -374,7 +419,7 @@ __device__ __forceinline__ void lean_fvs(R (*s)[PB][PB], int dir, int so, int sb
 
 template <class R>
 __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState un, MState out,
-                                                 double* __restrict__ centre, double dt, double ca, double cb,
+                                                 double* __restrict__ src, double dt, double ca, double cb,
                                                  Counters* cn, int bx, int by, R (*s)[PB][PB],
                                                  double* __restrict__ wslot) {
   constexpr bool F32 = IsF32<R>::value;
@@ -422,9 +467,9 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
     sts8(s, SY_, ty, tx, w);
   }
   __syncthreads();
-  // 1: centre values in FP64 (the last column/row's are never used); the
-  //    owner also stores its value for the cell kernel's source term.  Read
-  //    after the next barrier.
+  // 1: centre values in FP64 (the last column/row's are never used), read
+  //    by the line families after the next barrier; the owner of a cell
+  //    also writes the cell's nine-point source for the cell kernel.
   double C[NV];
   {
     double A[NV], Uc[NV], f[NV], w[NV], q[NV];
@@ -467,8 +512,33 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
     limit_centre(Uc, A, g.gm1, C, cn, owner);
     sts8(s, SC_, ty, tx, C);
     if (owner) {
+      // the cell's nine-point source for the cell kernel, from the tile's
+      // point values (in LDS since the barrier above) and this centre value
+      auto Bat = [&](int a, int b, R& b1, R& b2) {
+        if (a == 1 && b == 1) {
+          b1 = (R)C[4];
+          b2 = (R)C[5];
+          return;
+        }
+        const int base = b == 1 ? SX_ : (a == 1 ? SY_ : SV_);
+        const int yy = b == 2 ? tyu : ty, xx = a == 2 ? txr : tx;
+        b1 = s[base + 4][yy][xx];
+        b2 = s[base + 5][yy][xx];
+      };
+      auto Psiat = [&](int a, int b, R P[NV]) {
+        if (a == 1 && b == 1) {
+          psi(C, P);
+          return;
+        }
+        const int base = b == 1 ? SX_ : (a == 1 ? SY_ : SV_);
+        R w[NV];
+        lds8(s, base, b == 2 ? tyu : ty, a == 2 ? txr : tx, w);
+        psi(w, P);
+      };
+      R S[NV];
+      source_nine<R>(Bat, Psiat, (R)g.rdx, (R)g.rdy, S);
 #pragma unroll
-      for (int c = 0; c < NV; ++c) centre[c * g.sc + (long)j * g.nx + i] = C[c];
+      for (int c = 0; c < NV; ++c) src[c * g.sc + (long)j * g.nx + i] = (double)S[c];
     }
   }
   auto own_c = [&](double U[NV]) {
@@ -548,10 +618,10 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
 // the values it stores goes (a step's last stage).
 template <class R>
 __device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, MState out,
-                                            double* __restrict__ centre, double dt, double ca, double cb,
+                                            double* __restrict__ src, double dt, double ca, double cb,
                                             Counters* cn, int bx, int by, R (*s)[PB][PB],
                                             double* __restrict__ wslot = nullptr) {
-  points_tile_lean<R>(g, u, un, out, centre, dt, ca, cb, cn, bx, by, s, wslot);
+  points_tile_lean<R>(g, u, un, out, src, dt, ca, cb, cn, bx, by, s, wslot);
 }
 
 // ------------------------------------------------------ fused cell update
@@ -600,26 +670,13 @@ __device__ void sensor_from_prims(const R c[5], const R l[5], const R r[5], cons
   phi[3] = fabs(r[3] - l[3] + u[4] - d[4]) / (fabs(c[3] + c[4]) + tiny);
 }
 
-// Nine-point Powell source of cell (i,j), eq. (semi_av_src): weights
-// (1/6, 2/3, 1/6) per direction, the divergence at each sample point from
-// the one-sided / central differences of eq. (2d_fd) along the cell's rows
-// and columns, Psi at each point.  The centre sample is the limited centre
-// value, read from the buffer the point kernel fills.
+// The nine-point source of cell (i,j) from global memory, the centre value
+// C given (the cell kernel's ghost cells across an outflow boundary, whose
+// mirrored stencil is a computation of its own).
 template <class R>
-__device__ void cell_source(const Geo& g, CState u, const double* __restrict__ centre, int i, int j, R S[NV]) {
-  double C[NV];
-  ldA(g, centre, i, j, C);
-  // B1, B2 at the nine samples, [a][b] with a along x, b along y
-  R B1[3][3], B2[3][3];
-  auto ldB = [&](int a, int b, R& b1, R& b2) {
-    long off;
-    const double* base;
-    long plane;
-    if (a == 1 && b == 1) {
-      b1 = (R)C[4];
-      b2 = (R)C[5];
-      return;
-    } else if (b == 1) {
+__device__ void cell_source(const Geo& g, CState u, const double C[NV], int i, int j, R S[NV]) {
+  auto at = [&](int a, int b, const double*& base, long& plane, long& off) {
+    if (b == 1) {
       base = u.x, plane = g.sx, off = (long)map_cell(j, g.ny, g.bcy) * g.nxp + map_node(i + a / 2, g.nx, g.bcx);
     } else if (a == 1) {
       base = u.y, plane = g.sy, off = (long)map_node(j + b / 2, g.ny, g.bcy) * g.nx + map_cell(i, g.nx, g.bcx);
@@ -627,54 +684,54 @@ __device__ void cell_source(const Geo& g, CState u, const double* __restrict__ c
       base = u.v, plane = g.sv,
       off = (long)map_node(j + b / 2, g.ny, g.bcy) * g.nxp + map_node(i + a / 2, g.nx, g.bcx);
     }
+  };
+  auto Bat = [&](int a, int b, R& b1, R& b2) {
+    if (a == 1 && b == 1) {
+      b1 = (R)C[4];
+      b2 = (R)C[5];
+      return;
+    }
+    const double* base;
+    long plane, off;
+    at(a, b, base, plane, off);
     b1 = (R)base[4 * plane + off];
     b2 = (R)base[5 * plane + off];
   };
-#pragma unroll
-  for (int b = 0; b < 3; ++b)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) ldB(a, b, B1[a][b], B2[a][b]);
-  const R wq[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
-  const R rdx = (R)g.rdx, rdy = (R)g.rdy;
-  R f[9];
-#pragma unroll
-  for (int b = 0; b < 3; ++b)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const R dx1 = a == 0 ? (R(-3) * B1[0][b] + R(4) * B1[1][b] - B1[2][b])
-                  : a == 1 ? (B1[2][b] - B1[0][b])
-                           : (B1[0][b] - R(4) * B1[1][b] + R(3) * B1[2][b]);
-      const R dy2 = b == 0 ? (R(-3) * B2[a][0] + R(4) * B2[a][1] - B2[a][2])
-                  : b == 1 ? (B2[a][2] - B2[a][0])
-                           : (B2[a][0] - R(4) * B2[a][1] + R(3) * B2[a][2]);
-      f[3 * b + a] = wq[a] * wq[b] * (dx1 * rdx + dy2 * rdy);
+  auto Psiat = [&](int a, int b, R P[NV]) {
+    if (a == 1 && b == 1) {
+      psi(C, P);
+      return;
     }
-#pragma unroll
-  for (int c = 0; c < NV; ++c) S[c] = R(0);
-  // Three samples per trip: their loads are in flight together, while the
-  // states of all nine are never live together.
-#pragma unroll 3
-  for (int q = 0; q < 9; ++q) {
-    const int a = q % 3, b = q / 3;
-    R fq = f[0];
-#pragma unroll
-    for (int r = 1; r < 9; ++r) fq = q == r ? f[r] : fq;
+    const double* base;
+    long plane, off;
+    at(a, b, base, plane, off);
     double w[NV];
-    R P[NV];
-    if (q == 4) {
-#pragma unroll
-      for (int c = 0; c < NV; ++c) w[c] = C[c];
-    } else if (b == 1) {
-      ldX(g, u.x, i + a / 2, j, w);
-    } else if (a == 1) {
-      ldY(g, u.y, i, j + b / 2, w);
-    } else {
-      ldV(g, u.v, i + a / 2, j + b / 2, w);
-    }
+    load8(base, plane, off, w);
     psi(w, P);
+  };
+  source_nine<R>(Bat, Psiat, (R)g.rdx, (R)g.rdy, S);
+}
+
+// The centre value of cell (i,j) from global memory (Section 2.1, limited
+// as in remark rmk:cell_center), with the operations of the point tile's.
+__device__ void centre_value(const Geo& g, CState u, int i, int j, double C[NV]) {
+  double A[NV], Uc[NV], f[NV], w[NV], q[NV];
+  ldA(g, u.a, i, j, A);
+  ldX(g, u.x, i, j, f);
+  ldX(g, u.x, i + 1, j, w);
+  ldY(g, u.y, i, j, Uc);
+  ldY(g, u.y, i, j + 1, q);
 #pragma unroll
-    for (int c = 1; c < NV; ++c) S[c] += fq * P[c];
-  }
+  for (int c = 0; c < NV; ++c) f[c] = -4.0 * ((f[c] + w[c]) + (Uc[c] + q[c]));
+  ldV(g, u.v, i, j, Uc);
+  ldV(g, u.v, i + 1, j, w);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Uc[c] += w[c];
+  ldV(g, u.v, i, j + 1, q);
+  ldV(g, u.v, i + 1, j + 1, w);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Uc[c] = (36.0 * A[c] + f[c] - (Uc[c] + (q[c] + w[c]))) * 0.0625;
+  limit_centre(Uc, A, g.gm1, C, nullptr, false);
 }
 
 __device__ __forceinline__ int clamp_cell(int i, int n) { return i < -2 ? -2 : (i > n + 1 ? n + 1 : i); }
@@ -728,7 +785,7 @@ struct CellsLDS {
 
 // One tile of the cell update: CBX x CBY threads, (CBX-3) x (CBY-3) cells.
 template <class R, int CBX, int CBY>
-__device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double* __restrict__ centre,
+__device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double* __restrict__ src,
                                            const double* __restrict__ un, double* __restrict__ out, double dt,
                                            double ca, double cb, Counters* cn, int bx, int by,
                                            CellsLDS<R, CBX, CBY>& L, double* __restrict__ wslot = nullptr) {
@@ -744,7 +801,8 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   } else {
     s_lam = reinterpret_cast<double (*)[CBY][CBX]>(&L.x[0][0][0]);
   }
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * CBX + tx;
+  // thread (tx, ty) of the CBX x CBY tile: x fastest in the flat thread index
+  const int tid = (int)(threadIdx.y * blockDim.x + threadIdx.x), tx = tid % CBX, ty = tid / CBX;
   const int i0 = bx * (CBX - 3) - 1, j0 = by * (CBY - 3) - 1;
   const int i = clamp_cell(i0 + tx, g.nx), j = clamp_cell(j0 + ty, g.ny);
   const bool output = tx >= 1 && tx < CBX - 2 && ty >= 1 && ty < CBY - 2 && i0 + tx < g.nx && j0 + ty < g.ny;
@@ -807,9 +865,19 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
     divb = (prim[3 * PW * PH + pc + 1] - prim[3 * PW * PH + pc - 1]) * (0.5 * g.rdx);
     divb += (prim[4 * PW * PH + pc + PW] - prim[4 * PW * PH + pc - PW]) * (0.5 * g.rdy);
   }
-  // 2: nine-point source (before the interfaces: its temporaries and theirs
-  //    are never live together)
-  cell_source(g, u, centre, i, j, S);
+  // 2: nine-point source: the point kernel's for the grid's cells; a ghost
+  //    cell across an outflow boundary (its mirrored stencil differs from
+  //    its image's) computes its own
+  if ((g.bcx && (i < 0 || i >= g.nx)) || (g.bcy && (j < 0 || j >= g.ny))) {
+    double C[NV];
+    centre_value(g, u, i, j, C);
+    cell_source(g, u, C, i, j, S);
+  } else {
+    double Sd[NV];
+    ldA(g, src, i, j, Sd);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) S[c] = (R)Sd[c];
+  }
 #pragma unroll
   for (int c = 0; c < NV; ++c) G[c] = A[c];
 
@@ -929,7 +997,7 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
 #pragma unroll
   for (int c = 0; c < NV; ++c)
     An[c] = G[c] - dt * SL[c] + thL * H(0, c) + thR * H(1, c) + thD * H(2, c) + thU * H(3, c);
-  if (!in_G(An, g.gm1)) count(&cn->n_not_admissible);
+  if (!in_G_fast(An)) count(&cn->n_not_admissible);
   const long off = (long)j * g.nx + i;
   if (ca != 0.0) {
 #pragma unroll

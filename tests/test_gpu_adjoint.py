@@ -224,6 +224,45 @@ def test_checkpoint_segment_length_does_not_change_the_gradient(af):
         assert max(np.max(np.abs(a - b)) for a, b in zip(ga, gb)) <= 1e-12 * scale
 
 
+def test_backward_differentiates_the_returned_trajectory(af):
+    # The forward advances with the recording stage, so the backward's
+    # segment recomputation (from the checkpoints, with the same kernels)
+    # reproduces the forward's states bit for bit and freezes exactly the
+    # decisions the returned trajectory took.  Shock data with the sensor
+    # and the limiters active, 7 steps, checkpoints every 3.
+    import torch
+    prob = I.stirred(I.random_shock(20, 17, seed=2, bc=I.OUTFLOW))
+    u0 = af.to_device(I.sample(prob))
+    run = af.CheckpointedRun(prob, every=3)
+    uT = run.forward(u0, 7)
+    lam = tuple(torch.ones_like(t) for t in uT)
+    run.backward(lam)
+    torch.cuda.synchronize()
+    for a, b in zip(run.recomputed_end, uT):
+        assert torch.equal(a, b)
+    run.close()
+
+
+def test_forward_lands_on_the_final_time(af):
+    # With a finite t_final each step's dt is capped by the time remaining,
+    # and the run ends when the steps add up to t_final.
+    import torch
+    prob = I.alfven(16)
+    dt0 = None
+    for rf in (True, False):
+        run = af.CheckpointedRun(prob, record_forward=rf)
+        run.forward(af.to_device(I.sample(prob)), 6, t_final=0.02)
+        torch.cuda.synchronize()
+        n = run.nsteps
+        d = run.dts.cpu().numpy()[:n]
+        run.close()
+        if dt0 is None:
+            dt0 = d
+        assert 1 < n < 6
+        assert np.sum(d) == pytest.approx(0.02, rel=1e-14) and np.all(d > 0.0)
+        np.testing.assert_allclose(d, dt0, rtol=1e-13)
+
+
 def test_adjoint_argument_errors(af):
     import ctypes
     import torch
