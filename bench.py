@@ -246,6 +246,7 @@ def batched(af, I, args):
         shutil.copy(table, args.save_tile_table)
     return {"value": res["fp64"]["value"], "unit": UNIT, "instances": len(probs), "cells": cells,
             "ms_per_step": res["fp64"]["ms_per_step"], "graph": True,
+            "launches_per_stage": {"points": 1, "cells": 1}, "launches_per_step_dt": 2,
             "persistent": res["fp64"]["persistent"], "tiles": res["fp64"]["tiles"],
             "sequential_value": seq, "speedup_vs_sequential": res["fp64"]["value"] / seq,
             "fp32_bulk": res["fp32"], "fp32_speedup_vs_fp64": res["fp32"]["value"] / res["fp64"]["value"],
@@ -318,6 +319,7 @@ def adjoint(af, I, args):
            "objective": "J = 1/2 sum (rho(T) - 1)^2, gradient w.r.t. all 32 initial planes",
            "forward_ms": fwd_ms, "forward_with_checkpoints_ms": fwd_ckpt_ms, "backward_ms": bwd_ms,
            "adjoint_over_forward": (fwd_ckpt_ms + bwd_ms) / fwd_ms,
+           "forward_mode": "recording stage (the backward recomputes the same states bit for bit)",
            "checkpoint_every": every, "checkpoints": (nsteps + every - 1) // every,
            "tape_bytes_per_stage": tape_bytes, "J": J,
            "fd": {"directions": 20, "h": h, "max_rel": max(errs), "median_rel": float(np.median(errs))}}

@@ -765,8 +765,10 @@ __device__ __forceinline__ void interface_flux(const Geo& g, int dir, const doub
   }
 }
 
+// theta^s at an interface between the cells whose indicators are a[q] and
+// b[q] (q = phi1x, phi1y, phi2, phi3).
 template <class R>
-__device__ __forceinline__ R sensor_theta(R kappa, const R* a, const R* b, int dir) {
+__device__ __forceinline__ R sensor_theta(R kappa, const R a[4], const R b[4], int dir) {
   const R p1 = fmax(a[dir], b[dir]), p2 = fmax(a[2], b[2]), p3 = fmax(a[3], b[3]);
   return exp_r(-kappa * (p1 * p2 + p3));
 }
@@ -779,7 +781,7 @@ struct CellsLDS {
   R dfy[NV][CBY][CBX];  // ... at the y-interface below it; they give H_L, H_R, H_D, H_U
   R x[RF][CBY][CBX];    // exchange: primitives; records (0-3) and F^LLF (4-11); Lambda (FP64 stage)
   R ts[2][CBY][CBX];    // theta^s at the two interfaces
-  R phi[CBY + 1][CBX + 1][4];
+  R phi[4][CBY + 1][CBX + 1];  // indicator-major: a wavefront's lanes read consecutive words
   double lam[IsF32<R>::value ? 4 : 1][CBY][CBX];
 };
 
@@ -849,7 +851,7 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
     }
     sensor_from_prims(c, l, r, d, up, (R)g.dx, (R)g.dy, ph);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s_phi[b][a][q] = ph[q];
+    for (int q = 0; q < 4; ++q) s_phi[q][b][a] = ph[q];
   }
   __syncthreads();
 
@@ -921,8 +923,13 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
         ldY(g, u.y, i, j, w1);
         ldV(g, u.v, i + 1, j, w2);
       }
-      const R ts = dir == 0 ? sensor_theta(kappa, s_phi[ty + 1][tx], s_phi[ty + 1][tx + 1], 0)
-                            : sensor_theta(kappa, s_phi[ty][tx + 1], s_phi[ty + 1][tx + 1], 1);
+      R pa[4], pb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        pa[q] = dir == 0 ? s_phi[q][ty + 1][tx] : s_phi[q][ty][tx + 1];
+        pb[q] = s_phi[q][ty + 1][tx + 1];
+      }
+      const R ts = sensor_theta(kappa, pa, pb, dir);
       interface_flux(g, dir, w0, w1, w2, eN, AN, eA, A, ts, Fl, dF);
       s_ts[dir][ty][tx] = ts;
 #pragma unroll
