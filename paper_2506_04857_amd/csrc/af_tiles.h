@@ -835,6 +835,16 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
     }
   }
   __syncthreads();
+  // div B of the LLF source (phase 4) from the neighbours' B1, B2: for the
+  // FP64 stage from the sensor primitives (they hold B exactly), read before
+  // the next barrier, after which the exchange buffer they share is
+  // rewritten; for the FP32-bulk stage from memory in phase 4
+  double divb = 0.0;
+  if constexpr (!IsF32<R>::value) {
+    const int pc = (ty + 2) * PW + (tx + 2);
+    divb = (prim[3 * PW * PH + pc + 1] - prim[3 * PW * PH + pc - 1]) * (0.5 * g.rdx);
+    divb += (prim[4 * PW * PH + pc + PW] - prim[4 * PW * PH + pc - PW]) * (0.5 * g.rdy);
+  }
   // 1b: indicators on [i0-1, i0+CBX) x [j0-1, j0+CBY)
   for (int it = tid; it < (CBX + 1) * (CBY + 1); it += CNT) {
     const int a = it % (CBX + 1), b = it / (CBX + 1);
@@ -858,15 +868,6 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   double A[NV], G[NV];
   R S[NV];
   ldA(g, u.a, i, j, A);
-  // div B of the LLF source (phase 4) from the neighbours' B1, B2: for the
-  // FP64 stage from the sensor primitives still in LDS (they hold B exactly;
-  // phase 3 overwrites them), for the FP32-bulk stage from memory in phase 4
-  double divb = 0.0;
-  if constexpr (!IsF32<R>::value) {
-    const int pc = (ty + 2) * PW + (tx + 2);
-    divb = (prim[3 * PW * PH + pc + 1] - prim[3 * PW * PH + pc - 1]) * (0.5 * g.rdx);
-    divb += (prim[4 * PW * PH + pc + PW] - prim[4 * PW * PH + pc - PW]) * (0.5 * g.rdy);
-  }
   // 2: nine-point source: the point kernel's for the grid's cells; a ghost
   //    cell across an outflow boundary (its mirrored stencil differs from
   //    its image's) computes its own
@@ -885,10 +886,12 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
 
   // 3: interfaces.  dir 0: the x-interface left of the cell, dir 1: the
   //    y-interface below it.  The cell's record (1/rho, p, c_f, sqrt(rho))
-  //    goes through LDS (fields 0-3 of the exchange buffer); the neighbour
-  //    on the other side rebuilds the cell's directional evaluation from it
-  //    and the average it loads anyway.  The interface's LLF flux goes to
-  //    fields 4-11 for the cell on its other side.
+  //    goes to the neighbour on the other side, which rebuilds the cell's
+  //    directional evaluation from it and the average it loads anyway; the
+  //    interface's LLF flux goes back for that cell's update.  In x the two
+  //    cells are neighbouring lanes of one wavefront (a tile row is 16 or 32
+  //    lanes), so both travel by lane shuffles, with no barrier; in y they
+  //    go through LDS (fields 0-3 and 4-11 of the exchange buffer).
   const R kappa = (R)g.kappa;
   double w0[NV];  // V(i,j): the first edge point of both interfaces
   ldV(g, u.v, i, j, w0);
@@ -902,14 +905,24 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
       // the neighbour's average is loaded first: in flight across the barrier
       if (dir == 0) ldA(g, u.a, i - 1, j, AN); else ldA(g, u.a, i, j - 1, AN);
       rec_eval(A, g, dir, q);
+      if (dir == 1) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) s_x[c][ty][tx] = q[c];
+        for (int c = 0; c < 4; ++c) s_x[c][ty][tx] = q[c];
+      }
       rec_rebuild_d(A, dir, q, eA);
-      __syncthreads();
-      const int nx_ = dir == 0 ? tx - 1 : tx, ny_ = dir == 0 ? ty : ty - 1;
-      if ((dir == 0 ? tx : ty) > 0) {
+      if (dir == 0) {
+        // the left neighbour's record: lane tx - 1 (meaningless for tx = 0,
+        // which evaluates its neighbour itself)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) q[c] = s_x[c][ny_][nx_];
+        for (int c = 0; c < 4; ++c) q[c] = __shfl_up(q[c], 1);
+      } else {
+        __syncthreads();
+        if (ty > 0) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) q[c] = s_x[c][ty - 1][tx];
+        }
+      }
+      if ((dir == 0 ? tx : ty) > 0) {
         rec_rebuild_d(AN, dir, q, eN);
       } else {
         eval_dir(AN, g, dir, eN);
@@ -935,16 +948,23 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         (dir == 0 ? s_dfx : s_dfy)[c][ty][tx] = dF[c];
-        s_x[4 + c][ty][tx] = Fl[c];
+        if (dir == 1) s_x[4 + c][ty][tx] = Fl[c];
       }
     }
-    __syncthreads();
-    // the records of this direction are read and the fluxes published; the
-    // next direction's records and fluxes are written after its own barrier
     const double lam = dir == 0 ? lx : ly;
+    if (dir == 0) {
+      // the right neighbour's flux: lane tx + 1 (the last column, whose
+      // update is never used, takes its own)
 #pragma unroll
-    for (int c = 0; c < NV; ++c)
-      G[c] += lam * (double)(Fl[c] - (dir == 0 ? s_x[4 + c][ty][txr] : s_x[4 + c][tyu][tx]));
+      for (int c = 0; c < NV; ++c) {
+        const R fr = __shfl_down(Fl[c], 1);
+        G[c] += lam * (double)(Fl[c] - (tx + 1 < CBX ? fr : Fl[c]));
+      }
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < NV; ++c) G[c] += lam * (double)(Fl[c] - s_x[4 + c][tyu][tx]);
+    }
   }
   // H_I(c): anti-diffusive updates of the four interfaces
   auto H = [&](int I, int c) -> double {
