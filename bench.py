@@ -53,7 +53,8 @@ BYTES_PER_CELL_POINTS = 256 + 192 * 2.0 / 3.0 + 192
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILES = {"blast_lowbeta_1024": "k_points_k_cells_blast_lowbeta_1024_hbm_traffic.txt",
                  "orszag_tang_512": "k_points_k_cells_orszag_tang_512_hbm_traffic.txt"}
-VALU_FILES = {"blast_lowbeta_1024": "k_points_k_cells_blast_lowbeta_1024_valu.txt"}
+VALU_FILES = {"blast_lowbeta_1024": "k_points_k_cells_blast_lowbeta_1024_valu.txt",
+              "orszag_tang_512": "k_points_k_cells_orszag_tang_512_valu.txt"}
 CUS, CLOCK_HZ = 256, 2.4e9  # MI355X: one wave-instruction issued per CU per cycle at most
 
 
@@ -89,24 +90,34 @@ def profile_values(fname: str):
     return kv
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of the kernel from the committed rocprofv3
-    counter summary, or None."""
-    kv = profile_values(TRAFFIC_FILES.get(workload, ""))
-    try:
-        return float(kv["traffic_bytes_per_launch." + kernel])
-    except (TypeError, KeyError, ValueError):
+def stage_mean(kv, prefix: str, kernel: str):
+    """Per-launch value of a kernel averaged over the three stages of a step.
+    The stage kernels are instantiated twice: `<double, false>` runs stages
+    0 and 1, `<double, true>` the last stage, which also reduces the next
+    time step's wave speeds; a kernel with one instantiation is taken as is."""
+    if kv is None:
         return None
+    try:
+        if kernel.endswith("<double>"):
+            base = kernel[:-len("<double>")]
+            a = float(kv[f"{prefix}.{base}<double, false>"])
+            b = float(kv[f"{prefix}.{base}<double, true>"])
+            return (2.0 * a + b) / 3.0
+        return float(kv[f"{prefix}.{kernel}"])
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of the kernel (mean over a step's stages) from
+    the committed rocprofv3 counter summary, or None."""
+    return stage_mean(profile_values(TRAFFIC_FILES.get(workload, "")), "traffic_bytes_per_launch", kernel)
 
 
 def measured_valu(workload: str, kernel: str):
-    """VALU wave-instructions per launch of the kernel from the committed
-    SQ counter summary, or None."""
-    kv = profile_values(VALU_FILES.get(workload, ""))
-    try:
-        return float(kv["valu_insts_per_launch." + kernel])
-    except (TypeError, KeyError, ValueError):
-        return None
+    """VALU wave-instructions per launch of the kernel (mean over a step's
+    stages) from the committed SQ counter summary, or None."""
+    return stage_mean(profile_values(VALU_FILES.get(workload, "")), "valu_insts_per_launch", kernel)
 
 
 def cpu_baseline(prob, u0, budget_s=10.0):

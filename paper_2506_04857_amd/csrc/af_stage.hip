@@ -105,15 +105,18 @@ __global__ __launch_bounds__(BLK) void k_dt_final(const double* partial, int npa
   }
 }
 
-// dt from the per-workgroup maxima a step's last stage left (one workgroup).
-__global__ __launch_bounds__(BLK) void k_dt_from_parts(const double* wpart, int n, double cfl, double t_rem,
-                                                       double* dt) {
+// dt from the per-workgroup maxima a step's last stage left (one workgroup
+// of 1024 threads).
+constexpr int DT_PARTS_BLK = 1024;
+__global__ __launch_bounds__(DT_PARTS_BLK) void k_dt_from_parts(const double* wpart, int n, double cfl,
+                                                                double t_rem, double* dt) {
+  __shared__ double sh[DT_PARTS_BLK / 64];
   double m = 0.0;
 #pragma unroll 4
-  for (int t = threadIdx.x; t < n; t += BLK) m = fmax(m, wpart[t]);
-  m = block_max(m);
+  for (int t = threadIdx.x; t < n; t += DT_PARTS_BLK) m = fmax(m, wpart[t]);
+  block_max_store(m, (int)threadIdx.x, DT_PARTS_BLK, sh, sh);
   if (threadIdx.x == 0) {
-    double d = cfl / m;
+    double d = cfl / sh[0];
     *dt = d > t_rem ? t_rem : d;
   }
 }
@@ -442,7 +445,7 @@ int run_dt_from_parts(af_mhd_ctx* c, double t_rem, double* dt_dev) {
   hipEvent_t end;
   hipError_t e = timer_begin(c, KernelTimer::DT, &end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
-  k_dt_from_parts<<<1, BLK, 0, c->stream>>>(c->ws.wpart, c->ws.nwpart, c->g.cfl, t_rem, dt_dev);
+  k_dt_from_parts<<<1, DT_PARTS_BLK, 0, c->stream>>>(c->ws.wpart, c->ws.nwpart, c->g.cfl, t_rem, dt_dev);
   e = timer_end(c, end);
   if (e != hipSuccess) return fail(c, AF_EHIP, hipGetErrorString(e));
   return check_hip(c, "dt launch");

@@ -630,12 +630,15 @@ __device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, M
 // whose flux-limiter box is needed plus one trailing row/column whose left
 // and bottom interfaces close the region.  Per thread (cell (i,j)):
 //   1  shock-sensor indicators of the block's cells and one ring (LDS)
-//   2  x-interface at the cell's left: Simpson flux, LLF flux, sensor blend;
-//      exchanged through LDS so each cell has both of its x-interfaces
-//   3  the same for the bottom y-interface
-//   4  nine-point and LLF sources, flux-limiter steps (1)-(2) -> Lambda
-//   5  Lambda exchanged through LDS, unique interface coefficients, and the
-//      limited update in flux form written as
+//   2  the cell's nine-point source (written by the point kernel; ghost
+//      cells across an outflow boundary compute theirs)
+//   3  x-interface at the cell's left: Simpson flux, LLF flux, sensor blend;
+//      exchanged with the neighbouring lane so each cell has both of its
+//      x-interfaces; then the same for the bottom y-interface, through LDS
+//   4  LLF source, sensor blend of the source, flux-limiter steps (1)-(2)
+//      -> Lambda
+//   5  Lambda exchanged (lanes in x, LDS in y), unique interface
+//      coefficients, and the limited update in flux form written as
 //        A^new = G - dt S^Lim + sum_I theta_I H_I,
 //      G = A - dt/dx (F^LLF_R - F^LLF_L) - dt/dy (F^LLF_U - F^LLF_D),
 //      H_L = dt/dx (F^s_L - F^LLF_L), H_R = -dt/dx (F^s_R - F^LLF_R), ...
@@ -1006,14 +1009,17 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   for (int c = 0; c < NV; ++c) SL[c] = th * (double)S[c] + (1.0 - th) * (double)Sl[c];
   double Lam[4];
   limiter_box(A1, H, g.gm1, er, ep, Lam, cn, output);
-  // 5: unique interface coefficients and the limited update
-#pragma unroll
-  for (int I = 0; I < 4; ++I) s_lam[I][ty][tx] = Lam[I];
+  // 5: unique interface coefficients and the limited update: Lambda_R of
+  //    the left neighbour and Lambda_L of the right one by lane shuffles,
+  //    Lambda_U of the cell below and Lambda_D of the cell above through LDS
+  const double lamR_left = __shfl_up(Lam[1], 1), lamL_right = __shfl_down(Lam[0], 1);
+  s_lam[2][ty][tx] = Lam[2];
+  s_lam[3][ty][tx] = Lam[3];
   __syncthreads();
   double wm = 0.0;
   if (output) {
-  const double thL = fmin(s_lam[1][ty][tx - 1], Lam[0]);
-  const double thR = fmin(Lam[1], s_lam[0][ty][tx + 1]);
+  const double thL = fmin(lamR_left, Lam[0]);
+  const double thR = fmin(Lam[1], lamL_right);
   const double thD = fmin(s_lam[3][ty - 1][tx], Lam[2]);
   const double thU = fmin(Lam[3], s_lam[2][ty + 1][tx]);
   if (thL < 1.0) { count(&cn->n_theta_active); count_min_theta(cn, thL); }

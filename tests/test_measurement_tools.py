@@ -92,6 +92,20 @@ def test_bench_algorithmic_bytes_per_cell():
     assert bench.BYTES_PER_CELL_STAGE == pytest.approx(256 + 256 + 256 * 2 / 3)
 
 
+def test_bench_averages_the_last_stage_instantiation_over_a_step():
+    # stages 0 and 1 run `<double, false>`, the last stage `<double, true>`
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    kv = {"traffic_bytes_per_launch.k_points<double, false>": "600",
+          "traffic_bytes_per_launch.k_points<double, true>": "900",
+          "traffic_bytes_per_launch.k_dt_from_parts": "70"}
+    assert bench.stage_mean(kv, "traffic_bytes_per_launch", "k_points<double>") == pytest.approx(700.0)
+    assert bench.stage_mean(kv, "traffic_bytes_per_launch", "k_dt_from_parts") == pytest.approx(70.0)
+    assert bench.stage_mean(kv, "traffic_bytes_per_launch", "k_cells<double>") is None
+    assert bench.stage_mean(None, "traffic_bytes_per_launch", "k_points<double>") is None
+
+
 def test_bench_refuses_more_than_one_gpu():
     # the build runs on one GPU; bench.py --gpus N with N > 1 exits with a
     # message before touching any device
