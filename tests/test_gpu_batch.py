@@ -4,7 +4,8 @@ shape, plain launches or hipGraph replays) must be bitwise equal to the
 single-grid context's run on that instance, step by step.
 
 Each DoF's arithmetic is the same in both paths and the dt reduction is a
-max (order-independent), so equality is exact."""
+max (order-independent), so equality is exact.  The batch is also compared
+with the CPU oracle directly, to the 1e-11 parity bar."""
 import os
 import sys
 from dataclasses import replace
@@ -118,3 +119,44 @@ def test_batch_of_the_orszag_tang_ensemble_recipe(af):
     # perturbed fields): batch vs single grid, bitwise, one graph step.
     probs = I.batched_orszag_tang(6)
     check_batch(af, probs, 1, use_graph=True)
+
+
+def field_errors(got, want):
+    out = []
+    for g, w in zip(got, want):
+        for c in range(8):
+            scale = np.max(np.abs(w[c]))
+            d = np.max(np.abs(g[c] - w[c]))
+            out.append(d / scale if scale > 0 else d)
+    return max(out)
+
+
+@pytest.mark.parametrize("kind", ["mixed_kappa0_3_steps", "ensemble_kappa1_1_step"])
+def test_batch_against_the_oracle(af, oracle, kind):
+    # Every instance of a batch against the CPU oracle's steps directly (not
+    # only through the single-grid context): the same dt and every field to
+    # 1e-11 relative.  Multi-step comparisons use kappa = 0, where the scheme
+    # is well conditioned; the shock sensor is compared over one step of the
+    # benchmark ensemble's recipe.
+    import torch
+    if kind == "mixed_kappa0_3_steps":
+        probs, nsteps = [replace(p, kappa=0.0) for p in mixed_problems()], 3
+    else:
+        probs, nsteps = I.batched_orszag_tang(4), 1
+    u0s = [I.sample(p) for p in probs]
+    states = [af.to_device(u) for u in u0s]
+    b = af.Batch(probs, states)
+    refs = list(u0s)
+    worst = 0.0
+    for n in range(nsteps):
+        b.step(use_graph=True)
+        torch.cuda.synchronize()
+        dts = b.dt_dev.cpu().numpy()
+        for m, prob in enumerate(probs):
+            refs[m], dt = oracle.step(prob, refs[m])
+            assert abs(dts[m] - dt) <= 1e-12 * dt, f"step {n} instance {m}: dt {dts[m]!r} vs oracle {dt!r}"
+            e = field_errors(af.to_host(states[m]), refs[m])
+            worst = max(worst, e)
+            assert e <= 1e-11, f"step {n} instance {m} ({prob.name} {prob.nx}x{prob.ny}): {e:.3e}"
+    say(f"[batch] {kind}: {len(probs)} instances, {nsteps} steps, worst field rel err vs oracle {worst:.3e}")
+    b.close()
