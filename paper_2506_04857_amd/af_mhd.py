@@ -404,21 +404,27 @@ class CheckpointedRun:
     """n SSP-RK3 steps of one grid with the gradient of their end state by
     the discrete adjoint and sqrt(n) checkpointing.
 
-    forward(): the recording stage advances the state (its tape is not
-    kept), keeping the state every `every` steps (default ceil(sqrt(n))) and
-    the dt of every step in device memory.  backward(lam): for each segment,
-    last first, the recording stage recomputes the segment from its
-    checkpoint (keeping its stage inputs and tapes, 3 per step), then the
-    reverse sweep runs its steps backwards.  The recording stage is
-    deterministic, so the recomputation takes exactly the forward's
-    decisions and reproduces its states bit for bit: the gradient is that of
-    the trajectory forward() returned.  With record_forward=False the fast
-    stage kernels advance the forward instead (equal to the recording stage
-    only to rounding, so the decisions the backward freezes are those of a
-    trajectory within rounding of the returned one).  The dt sequence is data
+    forward(): the recording stage advances the state and the dt of every
+    step stays in device memory.  When every step's stage inputs and tapes
+    fit the memory budget (keep_tapes=None: half of the device memory free
+    when forward() starts; True: always; False: never) the forward keeps
+    them all and backward(lam) sweeps them in reverse order, so the
+    decisions the backward freezes are the forward's own tapes.  Otherwise
+    the forward keeps only the state every `every` steps (default
+    ceil(sqrt(n))) and its tapes go to one reusable buffer; backward(lam)
+    then recomputes each segment, last first, from its checkpoint with the
+    recording stage (stage inputs and tapes, 3 per step) before sweeping
+    it.  The recording stage is deterministic, so that recomputation takes
+    exactly the forward's decisions and reproduces its states bit for bit:
+    either way the gradient is that of the trajectory forward() returned.
+    With record_forward=False the fast stage kernels advance the forward
+    instead (equal to the recording stage only to rounding, so the decisions
+    the backward freezes are those of a trajectory within rounding of the
+    returned one; tapes are then never kept).  The dt sequence is data
     (frozen), not differentiated."""
 
-    def __init__(self, prob, device=None, every: int | None = None, record_forward: bool = True):
+    def __init__(self, prob, device=None, every: int | None = None, record_forward: bool = True,
+                 keep_tapes: bool | None = None):
         import torch
 
         self.prob = prob
@@ -427,6 +433,9 @@ class CheckpointedRun:
         self.adj = Adjoint(prob, device=self.device, stream=self.ctx.stream)
         self.every = every
         self.record_forward = record_forward
+        self.keep_tapes = keep_tapes
+        self.kept = None  # per step (U^n, U^(1), U^(2), tape0, tape1, tape2, dt) when the tapes are kept
+        self.tapes_kept = False
         self.dts = None
         self.checkpoints = []
         self.recomputed_end = None
@@ -473,20 +482,27 @@ class CheckpointedRun:
         u = tuple(t.clone() for t in u0)
         self.nsteps = nsteps
         self.checkpoints = []
+        self.kept = None
         if dts is not None:
             self.dts = dts.to(self.device, torch.float64).contiguous()
             assert self.dts.numel() >= nsteps
         else:
             self.dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=self.device)
-        s1, s2 = self._zeros(), self._zeros()
-        s3 = self._zeros() if self.record_forward else None
-        tape = self.adj.new_tape() if self.record_forward else None
+        keep = self.record_forward and self._keep(nsteps)
+        self.tapes_kept = keep
+        if keep:
+            self.kept = []
+        s1 = s2 = s3 = tape = None
+        if not keep:
+            s1, s2 = self._zeros(), self._zeros()
+            s3 = self._zeros() if self.record_forward else None
+            tape = self.adj.new_tape() if self.record_forward else None
         t = 0.0
         for s in range(nsteps):
             if math.isfinite(t_final) and t >= t_final:
                 self.nsteps = s  # t_final reached: the run ends here
                 break
-            if s % every == 0:
+            if s % every == 0 and not keep:
                 self.checkpoints.append(tuple(x.clone() for x in u))
             rem = t_final - t if math.isfinite(t_final) else float("inf")
             d = self.dts[s:s + 1]
@@ -494,10 +510,20 @@ class CheckpointedRun:
                 if dts is None:
                     self.ctx.af_mhd_dt(u, rem)
                     d.copy_(self.ctx.dt_dev)
-                self.adj.record(0, u, u, s1, d, tape)
-                self.adj.record(1, u, s1, s2, d, tape)
-                self.adj.record(2, u, s2, s3, d, tape)
-                u, s3 = s3, u
+                if keep:
+                    # the recording stage writes every element of its output
+                    s1, s2, s3 = self._empty(), self._empty(), self._empty()
+                    t0, t1, t2 = self.adj.new_tape(), self.adj.new_tape(), self.adj.new_tape()
+                    self.adj.record(0, u, u, s1, d, t0)
+                    self.adj.record(1, u, s1, s2, d, t1)
+                    self.adj.record(2, u, s2, s3, d, t2)
+                    self.kept.append((u, s1, s2, t0, t1, t2, d))
+                    u = s3
+                else:
+                    self.adj.record(0, u, u, s1, d, tape)
+                    self.adj.record(1, u, s1, s2, d, tape)
+                    self.adj.record(2, u, s2, s3, d, tape)
+                    u, s3 = s3, u
             elif dts is None:
                 self.ctx.af_mhd_step(u, rem)
                 d.copy_(self.ctx.dt_dev)
@@ -507,12 +533,41 @@ class CheckpointedRun:
                 self.ctx.af_mhd_stage(2, u, s2, u, d)
             if math.isfinite(t_final):
                 t += float(d.item())  # the time reached (one synchronisation per step)
+        if keep:
+            return tuple(x.clone() for x in u)  # the caller's; the kept inputs are the run's
         return u
+
+    def step_bytes(self) -> int:
+        """Device bytes one kept step holds: three stage inputs and three tapes."""
+        import math
+
+        state = 8 * sum(math.prod(s) for s in self.prob.shapes())
+        return 3 * state + 3 * (self.adj.tape_bytes + 256)
+
+    def _keep(self, nsteps: int) -> bool:
+        import torch
+
+        if self.keep_tapes is not None:
+            return bool(self.keep_tapes)
+        free, _ = torch.cuda.mem_get_info(self.device)
+        return nsteps * self.step_bytes() <= free // 2
 
     def backward(self, lam_T):
         """Adjoint of the initial state given lam_T, the adjoint of the end
         state (a tuple of 4 device tensors, not modified)."""
         lam = tuple(x.clone() for x in lam_T)
+        if self.kept is not None:
+            # the forward's own stage inputs and tapes, last step first; each
+            # is released once swept
+            while self.kept:
+                un, u1, u2, t0, t1, t2, d = self.kept.pop()
+                ln, l2, l1 = self._zero_states(3)
+                self.adj.stage(2, u2, t2, d, lam, ln, l2)
+                self.adj.stage(1, u1, t1, d, l2, ln, l1)
+                self.adj.stage(0, un, t0, d, l1, None, ln)
+                lam = ln
+            self.kept = None
+            return lam
         every = self.every
         for c in reversed(range(len(self.checkpoints))):
             first = c * every
@@ -542,21 +597,24 @@ class CheckpointedRun:
         return lam
 
     def close(self):
+        self.kept = None
+        self.checkpoints = []
         self.adj.close()
         self.ctx.close()
 
 
-def evolve(prob, u0, nsteps: int, every: int | None = None, dts=None):
+def evolve(prob, u0, nsteps: int, every: int | None = None, dts=None, keep_tapes: bool | None = None):
     """End state of nsteps SSP-RK3 steps from u0 (4 float64 device tensors)
     as a differentiable torch function: backward runs the discrete adjoint
-    with sqrt(n) checkpointing (decisions of the limiters and the sensor
-    frozen as the recomputation takes them, dt sequence fixed)."""
+    over the forward's kept tapes or with sqrt(n) checkpointing
+    (CheckpointedRun; decisions of the limiters and the sensor frozen as the
+    forward took them, dt sequence fixed)."""
     import torch
 
     class _Evolve(torch.autograd.Function):
         @staticmethod
         def forward(ctx, *u):
-            run = CheckpointedRun(prob, device=u[0].device, every=every)
+            run = CheckpointedRun(prob, device=u[0].device, every=every, keep_tapes=keep_tapes)
             out = run.forward(tuple(x.detach() for x in u), nsteps, dts=dts)
             ctx.run = run
             return out

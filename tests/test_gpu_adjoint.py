@@ -114,7 +114,7 @@ def test_recorded_stage_and_dot_products(af, oracle, name, make):
 
 def fixed_dt_sequence(af, prob, u0, nsteps):
     import torch
-    run = af.CheckpointedRun(prob)
+    run = af.CheckpointedRun(prob, keep_tapes=False)
     run.forward(af.to_device(u0), nsteps)
     torch.cuda.synchronize()
     dts = run.dts.clone()
@@ -122,10 +122,10 @@ def fixed_dt_sequence(af, prob, u0, nsteps):
     return dts
 
 
-def gradient(af, prob, u0, nsteps, dts, every=None):
+def gradient(af, prob, u0, nsteps, dts, every=None, keep_tapes=None):
     import torch
     u = tuple(t.requires_grad_(True) for t in af.to_device(u0))
-    uT = af.evolve(prob, u, nsteps, every=every, dts=dts)
+    uT = af.evolve(prob, u, nsteps, every=every, dts=dts, keep_tapes=keep_tapes)
     J = 0.5 * torch.sum((uT[0][0] - 1.0) ** 2)
     J.backward()
     torch.cuda.synchronize()
@@ -134,7 +134,7 @@ def gradient(af, prob, u0, nsteps, dts, every=None):
 
 def J_fixed(af, prob, u, nsteps, dts):
     import torch
-    run = af.CheckpointedRun(prob)
+    run = af.CheckpointedRun(prob, keep_tapes=False)
     uT = run.forward(af.to_device(u), nsteps, dts=dts)
     torch.cuda.synchronize()
     run.close()
@@ -148,7 +148,7 @@ def test_gradient_of_the_wave_kappa0(af, oracle):
     u0 = I.sample(prob)
     n = 12
     dts = fixed_dt_sequence(af, prob, u0, n)
-    grad, uT = gradient(af, prob, u0, n, dts, every=4)
+    grad, uT = gradient(af, prob, u0, n, dts, every=4, keep_tapes=False)
     dts_h = dts.cpu().numpy()[:n]
     uT_o, _ = oracle.tangent_run(prob, u0, [], dts_h)
     dirs = I.adjoint_directions(prob, 4)
@@ -175,7 +175,7 @@ def test_gradient_with_limiters_and_sensor(af, oracle):
     u0 = I.sample(prob)
     n = 4
     dts = fixed_dt_sequence(af, prob, u0, n)
-    grad, _ = gradient(af, prob, u0, n, dts, every=2)
+    grad, _ = gradient(af, prob, u0, n, dts, every=2, keep_tapes=False)
     dts_h = dts.cpu().numpy()[:n]
     uT_o, _ = oracle.tangent_run(prob, u0, [], dts_h)
     dirs = I.adjoint_directions(prob, 4)
@@ -202,7 +202,7 @@ def test_full_gradient_by_basis_sweep(af, oracle):
     u0 = I.sample(prob)
     n = 2
     dts = fixed_dt_sequence(af, prob, u0, n)
-    grad, _ = gradient(af, prob, u0, n, dts, every=1)
+    grad, _ = gradient(af, prob, u0, n, dts, every=1, keep_tapes=False)
     say("[adjoint] basis sweep 16x16 outflow: GPU gradient done")
     want, _ = basis_gradient(oracle, prob, u0, dts.cpu().numpy()[:n], chunk=1024,
                              progress=lambda i, m: say(f"[adjoint]   tangent oracle {i}/{m} directions"))
@@ -216,11 +216,13 @@ def test_checkpoint_segment_length_does_not_change_the_gradient(af):
     u0 = I.sample(prob)
     n = 9
     dts = fixed_dt_sequence(af, prob, u0, n)
-    g1, _ = gradient(af, prob, u0, n, dts, every=1)
-    g3, _ = gradient(af, prob, u0, n, dts, every=3)
-    g9, _ = gradient(af, prob, u0, n, dts, every=9)
+    # and the forward's kept tapes (no recomputation) give the same gradient
+    g1, _ = gradient(af, prob, u0, n, dts, every=1, keep_tapes=False)
+    g3, _ = gradient(af, prob, u0, n, dts, every=3, keep_tapes=False)
+    g9, _ = gradient(af, prob, u0, n, dts, every=9, keep_tapes=False)
+    gk, _ = gradient(af, prob, u0, n, dts, keep_tapes=True)
     scale = max(np.max(np.abs(a)) for a in g1)
-    for ga, gb in ((g1, g3), (g1, g9)):
+    for ga, gb in ((g1, g3), (g1, g9), (g1, gk)):
         assert max(np.max(np.abs(a - b)) for a, b in zip(ga, gb)) <= 1e-12 * scale
 
 
@@ -233,13 +235,22 @@ def test_backward_differentiates_the_returned_trajectory(af):
     import torch
     prob = I.stirred(I.random_shock(20, 17, seed=2, bc=I.OUTFLOW))
     u0 = af.to_device(I.sample(prob))
-    run = af.CheckpointedRun(prob, every=3)
+    run = af.CheckpointedRun(prob, every=3, keep_tapes=False)
     uT = run.forward(u0, 7)
     lam = tuple(torch.ones_like(t) for t in uT)
     run.backward(lam)
     torch.cuda.synchronize()
     for a, b in zip(run.recomputed_end, uT):
         assert torch.equal(a, b)
+    run.close()
+    # with the tapes kept the backward sweeps the forward's own stage inputs
+    run = af.CheckpointedRun(prob, keep_tapes=True)
+    uK = run.forward(u0, 7)
+    assert run.kept is not None and len(run.kept) == 7 and not run.checkpoints
+    for a, b in zip(uK, uT):
+        assert torch.equal(a, b)
+    run.backward(lam)
+    assert run.kept is None
     run.close()
 
 
