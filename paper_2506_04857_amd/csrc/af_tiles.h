@@ -152,9 +152,11 @@ __device__ __forceinline__ void acc_zero(PointAcc<R>& P) {
 // High-order and LLF states from the accumulators (the right-hand sides in
 // the compute type, the states in FP64), scaling limiter, SSP combination,
 // store.
+// Un: the point's U^n (used only when ca != 0), loaded by the caller one
+// phase ahead so that its latency overlaps other work.
 template <class R>
 __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[NV], const PointAcc<R>& P,
-                                      double ca, double cb, const double* __restrict__ un, double* __restrict__ out,
+                                      double ca, double cb, const double Un[NV], double* __restrict__ out,
                                       long plane, long off, Counters* cn, double* wmax) {
   double UH[NV], UL[NV], W[NV];
   R Ps[NV];
@@ -177,7 +179,7 @@ __device__ __forceinline__ void finish(const Geo& g, double dt, const double U0[
   if (!in_G_fast(W)) count(&cn->n_not_admissible);
   if (ca != 0.0) {
 #pragma unroll
-    for (int c = 0; c < NV; ++c) W[c] = ca * un[c * plane + off] + cb * W[c];
+    for (int c = 0; c < NV; ++c) W[c] = ca * Un[c] + cb * W[c];
   }
 #pragma unroll
   for (int c = 0; c < NV; ++c) out[c * plane + off] = W[c];
@@ -572,11 +574,12 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
   lean_records(s, g, ty, tx, w, w2, 0);
   __syncthreads();
   lean_fvs<R, false>(s, 0, SX_, SC_, ty, tx, ty, txl, ty, txr, rdx, lxr, PX, PX);
-  if (outX) {
-    own(1, w);
-    finish(g, dt, w, PX, ca, cb, un.x, out.x, g.sx, (long)j * g.nxp + i, cn, wmax);
-  }
+  // X is complete; its U^n is loaded now and X finished after the next
+  // family's records, while the load is in flight
+  double unp[NV];
+  if (outX && ca != 0.0) ldX(g, un.x, i, j, unp);
   pin_acc(PV);
+  pin_acc(PX);
   __syncthreads();
 
   // a: horizontal lines through V and Y.  V: FVS in x over V(k-1), Y(k-1),
@@ -586,13 +589,16 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
   own(2, w2);
   lean_records(s, g, ty, tx, w, w2, 0);
   __syncthreads();
+  if (outX) {
+    own(1, w);
+    finish(g, dt, w, PX, ca, cb, unp, out.x, g.sx, (long)j * g.nxp + i, cn, wmax);
+  }
   acc_zero(PY);
   lean_fvs<R, true>(s, 0, SV_, SY_, ty, tx, ty, txl, ty, txr, rdx, lxr, PV, PY);
   pin_acc(PY);
-  if (outV) {
-    own(0, w);
-    finish(g, dt, w, PV, ca, cb, un.v, out.v, g.sv, (long)j * g.nxp + i, cn, wmax);
-  }
+  // V is complete: the same for V over the next family's records
+  if (outV && ca != 0.0) ldV(g, un.v, i, j, unp);
+  pin_acc(PV);
   __syncthreads();
 
   // d: vertical lines through Y and C.  Y: FVS in y over Y(l-1), C(l-1), Y,
@@ -601,10 +607,16 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
   own_c(w2);
   lean_records(s, g, ty, tx, w, w2, 1);
   __syncthreads();
+  if (outV) {
+    own(0, w);
+    finish(g, dt, w, PV, ca, cb, unp, out.v, g.sv, (long)j * g.nxp + i, cn, wmax);
+  }
+  // Y's U^n: in flight during the family's line sums
+  if (outY && ca != 0.0) ldY(g, un.y, i, j, unp);
   lean_fvs<R, false>(s, 1, SY_, SC_, ty, tx, tyd, tx, tyu, tx, rdy, lyr, PY, PY);
   if (outY) {
     own(2, w);
-    finish(g, dt, w, PY, ca, cb, un.y, out.y, g.sy, (long)j * g.nx + i, cn, wmax);
+    finish(g, dt, w, PY, ca, cb, unp, out.y, g.sy, (long)j * g.nx + i, cn, wmax);
   }
   if (wslot) {
     __syncthreads();  // the LDS is reused as the reduction's scratch
@@ -848,6 +860,12 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
     divb = (prim[3 * PW * PH + pc + 1] - prim[3 * PW * PH + pc - 1]) * (0.5 * g.rdx);
     divb += (prim[4 * PW * PH + pc + PW] - prim[4 * PW * PH + pc - PW]) * (0.5 * g.rdy);
   }
+  // the cell's average, nine-point source and first edge point: loaded
+  // now, in flight while the indicators are computed
+  double A[NV], Sd[NV], w0[NV];
+  ldA(g, u.a, i, j, A);
+  ldA(g, src, i, j, Sd);
+  ldV(g, u.v, i, j, w0);
   // 1b: indicators on [i0-1, i0+CBX) x [j0-1, j0+CBY)
   for (int it = tid; it < (CBX + 1) * (CBY + 1); it += CNT) {
     const int a = it % (CBX + 1), b = it / (CBX + 1);
@@ -868,9 +886,8 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   }
   __syncthreads();
 
-  double A[NV], G[NV];
+  double G[NV];
   R S[NV];
-  ldA(g, u.a, i, j, A);
   // 2: nine-point source: the point kernel's for the grid's cells; a ghost
   //    cell across an outflow boundary (its mirrored stencil differs from
   //    its image's) computes its own
@@ -879,8 +896,6 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
     centre_value(g, u, i, j, C);
     cell_source(g, u, C, i, j, S);
   } else {
-    double Sd[NV];
-    ldA(g, src, i, j, Sd);
 #pragma unroll
     for (int c = 0; c < NV; ++c) S[c] = (R)Sd[c];
   }
@@ -896,17 +911,25 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   //    lanes), so both travel by lane shuffles, with no barrier; in y they
   //    go through LDS (fields 0-3 and 4-11 of the exchange buffer).
   const R kappa = (R)g.kappa;
-  double w0[NV];  // V(i,j): the first edge point of both interfaces
-  ldV(g, u.v, i, j, w0);
+  // w0 = V(i,j): the first edge point of both interfaces
 #pragma unroll
   for (int dir = 0; dir < 2; ++dir) {
     R Fl[NV];
     {
       DirEvalT<R> eA, eN;
-      double AN[NV];
+      double AN[NV], w1[NV], w2[NV];
       R q[4];
-      // the neighbour's average is loaded first: in flight across the barrier
-      if (dir == 0) ldA(g, u.a, i - 1, j, AN); else ldA(g, u.a, i, j - 1, AN);
+      // the neighbour's average and the interface's edge points are loaded
+      // first, together: in flight across the record exchange
+      if (dir == 0) {
+        ldA(g, u.a, i - 1, j, AN);
+        ldX(g, u.x, i, j, w1);
+        ldV(g, u.v, i, j + 1, w2);
+      } else {
+        ldA(g, u.a, i, j - 1, AN);
+        ldY(g, u.y, i, j, w1);
+        ldV(g, u.v, i + 1, j, w2);
+      }
       rec_eval(A, g, dir, q);
       if (dir == 1) {
 #pragma unroll
@@ -930,15 +953,7 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
       } else {
         eval_dir(AN, g, dir, eN);
       }
-      double w1[NV], w2[NV];
       R dF[NV];
-      if (dir == 0) {
-        ldX(g, u.x, i, j, w1);
-        ldV(g, u.v, i, j + 1, w2);
-      } else {
-        ldY(g, u.y, i, j, w1);
-        ldV(g, u.v, i + 1, j, w2);
-      }
       R pa[4], pb[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
