@@ -451,7 +451,8 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
     }
   };
 
-  // 0: the tile's raw point values into LDS
+  // 0: the tile's raw point values into LDS, and the records of family b
+  //    (below) of the thread's own V and X, from the values loaded
   if constexpr (F32) {
     ldV(g, u.v, i, j, oV);
     sts8(s, SV_, ty, tx, oV);
@@ -459,23 +460,38 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
     sts8(s, SX_, ty, tx, oX);
     ldY(g, u.y, i, j, oY);
     sts8(s, SY_, ty, tx, oY);
+    lean_records(s, g, ty, tx, oV, oX, 1);
   } else {
-    double w[NV];
-    ldV(g, u.v, i, j, w);
-    sts8(s, SV_, ty, tx, w);
-    ldX(g, u.x, i, j, w);
-    sts8(s, SX_, ty, tx, w);
+    double wv[NV], wx[NV], w[NV];
+    ldV(g, u.v, i, j, wv);
+    ldX(g, u.x, i, j, wx);
     ldY(g, u.y, i, j, w);
+    sts8(s, SV_, ty, tx, wv);
+    sts8(s, SX_, ty, tx, wx);
     sts8(s, SY_, ty, tx, w);
+    lean_records(s, g, ty, tx, wv, wx, 1);
   }
+  // the cell average of the centre value, in flight during family b
+  double A[NV];
+  ldA(g, u.a, i, j, A);
   __syncthreads();
+  PointAcc<R> PV, PX, PY;
+
+  // b: vertical lines through V and X.  V: FVS in y over V(l-1), X(l-1), V,
+  // X(l), V(l+1).  X: central in y between V(k,j) and V(k,j+1).  It reads
+  // no centre value, so it shares its barrier interval with phase 1.
+  acc_zero(PV);
+  acc_zero(PX);
+  lean_fvs<R, true>(s, 1, SV_, SX_, ty, tx, tyd, tx, tyu, tx, rdy, lyr, PV, PX);
+  pin_acc(PV);
+  pin_acc(PX);
+
   // 1: centre values in FP64 (the last column/row's are never used), read
-  //    by the line families after the next barrier; the owner of a cell
-  //    also writes the cell's nine-point source for the cell kernel.
+  //    by the line families c and d after the next barrier; the owner of a
+  //    cell also writes the cell's nine-point source for the cell kernel.
   double C[NV];
   {
-    double A[NV], Uc[NV], f[NV], w[NV], q[NV];
-    ldA(g, u.a, i, j, A);
+    double Uc[NV], f[NV], w[NV], q[NV];
     if constexpr (F32) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) f[c] = oX[c];
@@ -551,18 +567,7 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
       lds8(s, SC_, ty, tx, U);
     }
   };
-  PointAcc<R> PV, PX, PY;
   double w[NV], w2[NV];
-
-  // b: vertical lines through V and X.  V: FVS in y over V(l-1), X(l-1), V,
-  // X(l), V(l+1).  X: central in y between V(k,j) and V(k,j+1).
-  own(0, w);
-  own(1, w2);
-  lean_records(s, g, ty, tx, w, w2, 1);
-  __syncthreads();
-  acc_zero(PV);
-  acc_zero(PX);
-  lean_fvs<R, true>(s, 1, SV_, SX_, ty, tx, tyd, tx, tyu, tx, rdy, lyr, PV, PX);
   pin_acc(PV);
   pin_acc(PX);
   __syncthreads();
