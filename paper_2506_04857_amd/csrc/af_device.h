@@ -492,6 +492,9 @@ __device__ void limiter_box(const double A1[NV], HF H, double gm1, double er, do
   }
   double rmin[4] = {1.0, 1.0, 1.0, 1.0};
   bool any_root = false;
+  // the vertex loops stay rolled: they run only where the shortcut fails,
+  // and unrolled they cost the fast path its registers (spills)
+#pragma unroll 1
   for (int k = 1; k < 16; ++k) {
     double D[NV], W[NV];
 #pragma unroll
@@ -520,6 +523,7 @@ __device__ void limiter_box(const double A1[NV], HF H, double gm1, double er, do
   for (int I = 0; I < 4; ++I) Lam[I] = Lr[I] * rmin[I];
   if (!any_root) return;
   auto box_ok = [&](const double L[4]) {
+#pragma unroll 1
     for (int k = 1; k < 16; ++k) {
       double W[NV];
 #pragma unroll
