@@ -196,14 +196,16 @@ def timed_steps(ctx, u, steps, stream):
 
 
 TILE_TABLE = os.path.join(ROOT, "paper_2506_04857_amd", "tiles_mi355x.txt")
+MODE_NAMES = {0: "flat", 1: "persistent", 2: "fused"}
 
 
 def batched(af, I, args):
     """The batched Orszag-Tang ensemble: 256 instances of sizes drawn from
     {64,96,128,192,256}^2 with perturbed fields, all stepped together (one
-    hipGraph per step; cell tiles from the autotuned table), FP64 and
-    FP32-bulk; against the same instances stepped one after another by
-    single-grid contexts."""
+    hipGraph per step; cell tiles from the autotuned table; the launch mode
+    the batch's tuner picks, and each of the three modes timed on the same
+    batch), FP64 and FP32-bulk; against the same instances stepped one after
+    another by single-grid contexts."""
     import shutil
     import tempfile
 
@@ -232,8 +234,26 @@ def batched(af, I, args):
         for m in range(len(probs)):
             key = "%dx%d" % b.tile(m)
             tiles[key] = tiles.get(key, 0) + 1
+        chosen = b.launch_mode()
         res[name] = {"value": cells * 3 * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
-                     "persistent": b.persistent(), "tiles": tiles}
+                     "mode": MODE_NAMES[chosen], "persistent": b.persistent(), "tiles": tiles}
+        if name == "fp64":
+            # every launch mode on the same batch (graph replays, 20 steps each)
+            modes = {}
+            for mode in (af.AF_BATCH_FLAT, af.AF_BATCH_PERSISTENT, af.AF_BATCH_FUSED):
+                b.set_launch_mode(mode)
+                for _ in range(2):
+                    b.step()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(b.stream)
+                for _ in range(20):
+                    b.step()
+                e1.record(b.stream)
+                torch.cuda.synchronize()
+                modes[MODE_NAMES[mode]] = {"value": cells * 3 * 20 / (e0.elapsed_time(e1) * 1e-3),
+                                           "launches_per_stage": 1 if mode == af.AF_BATCH_FUSED else 2}
+            res[name]["modes"] = modes
         b.close()
         del states
     # the same instances one after another, single-grid contexts, FP64
@@ -256,8 +276,9 @@ def batched(af, I, args):
     if args.save_tile_table:
         shutil.copy(table, args.save_tile_table)
     return {"value": res["fp64"]["value"], "unit": UNIT, "instances": len(probs), "cells": cells,
-            "ms_per_step": res["fp64"]["ms_per_step"], "graph": True,
-            "launches_per_stage": {"points": 1, "cells": 1}, "launches_per_step_dt": 2,
+            "ms_per_step": res["fp64"]["ms_per_step"], "graph": True, "mode": res["fp64"]["mode"],
+            "launches_per_stage": 1 if res["fp64"]["mode"] == "fused" else 2, "launches_per_step_dt": 2,
+            "modes": res["fp64"]["modes"],
             "persistent": res["fp64"]["persistent"], "tiles": res["fp64"]["tiles"],
             "sequential_value": seq, "speedup_vs_sequential": res["fp64"]["value"] / seq,
             "fp32_bulk": res["fp32"], "fp32_speedup_vs_fp64": res["fp32"]["value"] / res["fp64"]["value"],

@@ -247,14 +247,25 @@ int af_mhd_step_noalloc(const af_mhd_params* p, af_mhd_state* u, double t_remain
  * A batch advances n independent grids together (each with its own
  * parameters: sizes, domain, gamma, cfl, kappa, boundaries; the flags must
  * agree).  Per SSP-RK3 step it runs one launch computing every instance's
- * dt (min(cfl / max wave speed, t_remaining)), then per stage one launch of
- * the point update over the (instance, tile) work items of all instances and
- * one launch of the cell update over theirs (32 x 16 or 16 x 32 cell tiles:
- * the shape tuned for the size classes holding most of the batch's cells);
- * the step can be captured once into a hipGraph and replayed.  Each
- * instance's results are bitwise equal to what a single-grid context
- * computes on it. */
+ * dt (min(cfl / max wave speed, t_remaining)), then per stage, by launch
+ * mode (af_mhd_batch_set_launch_mode):
+ *   AF_BATCH_FUSED       one launch over the point tiles of all instances
+ *                        (two per 512-thread workgroup) and their cell tiles,
+ *                        which compute their cells' nine-point sources
+ *                        themselves, so that no workgroup waits on another;
+ *   AF_BATCH_PERSISTENT  one launch of the point update over the (instance,
+ *                        tile) work items of all instances and one of the
+ *                        cell update over theirs, persistent workgroups;
+ *   AF_BATCH_FLAT        the same two launches, one item per workgroup.
+ * Cell tiles are 32 x 16 or 16 x 32: the shape tuned for the size classes
+ * holding most of the batch's cells.  The step can be captured once into a
+ * hipGraph and replayed.  Each instance's results are bitwise equal to
+ * what a single-grid context computes on it, in every mode. */
 typedef struct af_mhd_batch af_mhd_batch;
+
+#define AF_BATCH_FLAT 0
+#define AF_BATCH_PERSISTENT 1
+#define AF_BATCH_FUSED 2
 
 /* Bytes of device workspace for n instances with parameters p[0..n-1]
  * (two RK scratch states and a nine-point source buffer per instance, dt partials,
@@ -284,12 +295,17 @@ int af_mhd_batch_step(af_mhd_batch* b, int use_graph);
  * instance m runs on (the same for every m). */
 int af_mhd_batch_tile(const af_mhd_batch* b, int m, int* tile_x, int* tile_y);
 
-/* Launch mode of the stage kernels: 1 persistent (about one resident wave
- * of workgroups stepping through the work items), 0 one work item per
- * workgroup.  One item per workgroup by default (the persistent loop costs
- * the cell kernel registers); with a tune table, the faster of the two on
- * this batch (measured at init on stage-0 launches). */
-int af_mhd_batch_launch_mode(const af_mhd_batch* b, int* persistent);
+/* Launch mode of the stages (AF_BATCH_FLAT, AF_BATCH_PERSISTENT or
+ * AF_BATCH_FUSED, described above) into *mode.  AF_BATCH_FLAT by default;
+ * with a tune table, the fastest of the three on this batch (measured at
+ * init on stage-0 launches). */
+int af_mhd_batch_launch_mode(const af_mhd_batch* b, int* mode);
+
+/* Set the launch mode of the following steps (a graph captured in another
+ * mode is dropped and the next graph step captures anew).  AF_EINVAL for
+ * an unknown mode. */
+int af_mhd_batch_set_launch_mode(af_mhd_batch* b, int mode);
+
 
 /* Limiter counters accumulated over all instances since init (the state
  * statistics fields of out are left zero).  Synchronises the stream. */

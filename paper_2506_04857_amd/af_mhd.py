@@ -54,6 +54,7 @@ class af_mhd_stats_t(ctypes.Structure):
 AF_FLAG_FP32_BULK = 1
 AF_FLAG_KERNEL_TIMING = 4
 AF_FLAG_FUSED_DT = 8
+AF_BATCH_FLAT, AF_BATCH_PERSISTENT, AF_BATCH_FUSED = 0, 1, 2
 
 
 class af_mhd_kernel_times_t(ctypes.Structure):
@@ -108,6 +109,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.af_mhd_batch_tile.restype = ctypes.c_int
     L.af_mhd_batch_launch_mode.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.af_mhd_batch_launch_mode.restype = ctypes.c_int
+    L.af_mhd_batch_set_launch_mode.argtypes = [vp, ctypes.c_int]
+    L.af_mhd_batch_set_launch_mode.restype = ctypes.c_int
     L.af_mhd_batch_counters.argtypes = [vp, ST]
     L.af_mhd_batch_counters.restype = ctypes.c_int
     L.af_mhd_batch_destroy.argtypes = [vp]
@@ -316,10 +319,18 @@ class Batch:
         self._check(_lib.af_mhd_batch_tile(self._h, m, ctypes.byref(tx), ctypes.byref(ty)))
         return tx.value, ty.value
 
-    def persistent(self) -> bool:
+    def launch_mode(self) -> int:
+        """AF_BATCH_FLAT, AF_BATCH_PERSISTENT or AF_BATCH_FUSED."""
         p = ctypes.c_int()
         self._check(_lib.af_mhd_batch_launch_mode(self._h, ctypes.byref(p)))
-        return bool(p.value)
+        return p.value
+
+    def set_launch_mode(self, mode: int):
+        self._check(_lib.af_mhd_batch_set_launch_mode(self._h, int(mode)))
+
+    def persistent(self) -> bool:
+        """Whether the stages run on persistent workgroups."""
+        return self.launch_mode() == AF_BATCH_PERSISTENT
 
     def counters(self) -> dict:
         st = af_mhd_stats_t()

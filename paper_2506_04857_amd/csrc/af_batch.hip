@@ -1,10 +1,17 @@
 // af_batch.hip -- batched ensembles: many independent grids, of any sizes,
 // advanced together.  Per SSP-RK3 step: one launch for the dt of every
-// instance (plus its per-instance finish), then per stage one launch of the
-// point update over the (instance, tile) work items of all instances and one
-// launch of the cell update over theirs (32 x 16 or 16 x 32 tiles: the
-// shape tuned for most of the batch's cells); persistent workgroups or one
-// item per workgroup, whichever is faster on the batch.  The step is captured once into a
+// instance (plus its per-instance finish), then per stage either
+//   - one launch (AF_BATCH_FUSED) over the point tiles of all instances
+//     (two 16 x 16 tiles per 512-thread workgroup) and their cell tiles,
+//     which compute their own nine-point sources so that nothing in the
+//     launch waits on anything, or
+//   - one launch of the point update over the (instance, tile) work items
+//     of all instances and one launch of the cell update over theirs, with
+//     persistent workgroups (AF_BATCH_PERSISTENT) or one item per workgroup
+//     (AF_BATCH_FLAT).
+// Cell tiles are 32 x 16 or 16 x 32 (the shape tuned for most of the
+// batch's cells).  The mode is the fastest on the batch's stage 0, measured
+// at init, unless the caller sets one.  The step is captured once into a
 // hipGraph and replayed.  The cell-tile shape of each grid size is chosen
 // by measurement (autotune) and kept in a text table that later runs reuse.
 //
@@ -124,6 +131,51 @@ __global__ __launch_bounds__(CBX * CBY) void kb_cells(const BInst* __restrict__ 
   }
 }
 
+// One stage of every instance in one launch (AF_BATCH_FUSED): workgroups
+// [0, npairs) take pairs of point tiles (tiles 2q and 2q+1 of the batch's
+// point list, run side by side by the two halves of the 512-thread
+// workgroup; an odd last tile leaves the second half recomputing the first
+// half's tile without storing anything), workgroups [npairs, npairs +
+// citems) cell tiles.  The two kinds share nothing within the stage: the
+// cell tiles compute their cells' nine-point sources themselves, from the
+// stage input, instead of reading the point tiles' (which would make a cell
+// tile wait for its neighbours' point tiles), so the launch has no
+// inter-workgroup synchronisation at all.
+constexpr int FUSED_THREADS = 512;
+
+template <class R, int CBX, int CBY>
+__global__ __launch_bounds__(FUSED_THREADS) void kb_stage(const BInst* __restrict__ P, const BInst* __restrict__ C,
+                                                          int n, int pitems, int citems, double ca, double cb,
+                                                          Counters* cn) {
+  static_assert(CBX * CBY == FUSED_THREADS, "one cell tile per workgroup");
+  union Lds {
+    R pts[2][point_fields<R>()][PB][PB];
+    CellsLDS<R, CBX, CBY> cells;
+  };
+  __shared__ Lds L;
+  const int tid = (int)(threadIdx.y * blockDim.x + threadIdx.x);
+  const int npairs = (pitems + 1) / 2;
+  const int it = (int)blockIdx.x;
+  if (it < npairs) {
+    const int half = tid / PNT, ltid = tid % PNT;
+    const int t0 = 2 * it + half;
+    const bool live = t0 < pitems;
+    const int t = live ? t0 : 2 * it;
+    const int m = find_inst(P, n, t);
+    const Geo g = P[m].g;
+    const int tt = t - P[m].first, ntx = P[m].ntx;
+    points_tile_lean<R>(g, P[m].u, P[m].un, P[m].out, nullptr, *P[m].dt, ca, cb, cn, tt % ntx, tt / ntx,
+                        L.pts[half], nullptr, ltid % PB, ltid / PB, live);
+    return;
+  }
+  const int c = it - npairs;
+  if (c >= citems) return;
+  const int m = find_inst(C, n, c);
+  const int t = c - C[m].first, ntx = C[m].ntx;
+  cells_tile<R, CBX, CBY>(C[m].g, C[m].u, nullptr, C[m].un.a, C[m].out.a, *C[m].dt, ca, cb, cn, t % ntx, t / ntx,
+                          L.cells);
+}
+
 // dt: partial maxima of rho_1/dx + rho_2/dy over DT_CHUNK DoFs per item,
 // then one workgroup per instance.
 __global__ __launch_bounds__(BLK) void kb_dt_partial(const BDt* __restrict__ D, int n, int items,
@@ -194,6 +246,13 @@ void launch_points(bool persist, int grid, hipStream_t s, const BInst* I, int n,
 }
 
 template <class R>
+void launch_fused(int shape, hipStream_t s, const BInst* P, const BInst* C, int n, int pitems, int citems,
+                  double ca, double cb, Counters* cn) {
+  const int grid = (pitems + 1) / 2 + citems;  // one work item per workgroup
+  if (shape == 0) kb_stage<R, 32, 16><<<grid, dim3(32, 16), 0, s>>>(P, C, n, pitems, citems, ca, cb, cn);
+  else kb_stage<R, 16, 32><<<grid, dim3(32, 16), 0, s>>>(P, C, n, pitems, citems, ca, cb, cn);
+}
+template <class R>
 const void* cells_fn(int shape) {
   return shape == 0 ? reinterpret_cast<const void*>(&kb_cells<R, 32, 16, true>)
                     : reinterpret_cast<const void*>(&kb_cells<R, 16, 32, true>);
@@ -231,7 +290,7 @@ struct af_mhd_batch {
   double* partial = nullptr;
   Counters* cnt = nullptr;
   int grid_points = 0, grid_cells = 0, grid_dt = 0;
-  bool persist = false;                 // persistent or flat stage launches
+  int mode = AF_BATCH_FLAT;             // launch mode of the stages
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string err;
@@ -415,6 +474,23 @@ int build_tables(af_mhd_batch* b) {
   return bcheck(b, e, "batch tables");
 }
 
+// The launches of stage k in the batch's mode.
+void enqueue_stage(af_mhd_batch* b, int k, double a, double c) {
+  hipStream_t s = b->stream;
+  if (b->mode == AF_BATCH_FUSED) {
+    if (b->f32)
+      launch_fused<float>(b->cshape, s, b->pts[k], b->cls[k], b->n, b->pts_items, b->cls_items, a, c, b->cnt);
+    else
+      launch_fused<double>(b->cshape, s, b->pts[k], b->cls[k], b->n, b->pts_items, b->cls_items, a, c, b->cnt);
+    return;
+  }
+  const bool persist = b->mode == AF_BATCH_PERSISTENT;
+  if (b->f32) launch_points<float>(persist, b->grid_points, s, b->pts[k], b->n, b->pts_items, a, c, b->cnt);
+  else launch_points<double>(persist, b->grid_points, s, b->pts[k], b->n, b->pts_items, a, c, b->cnt);
+  if (b->f32) launch_cells<float>(persist, b->cshape, b->grid_cells, s, b->cls[k], b->n, b->cls_items, a, c, b->cnt);
+  else launch_cells<double>(persist, b->cshape, b->grid_cells, s, b->cls[k], b->n, b->cls_items, a, c, b->cnt);
+}
+
 // The launches of one step (also what the graph records).
 int enqueue_step(af_mhd_batch* b) {
   static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
@@ -422,18 +498,7 @@ int enqueue_step(af_mhd_batch* b) {
   hipStream_t s = b->stream;
   kb_dt_partial<<<b->grid_dt, BLK, 0, s>>>(b->dts, b->n, b->dt_items, b->partial);
   kb_dt_final<<<b->n, BLK, 0, s>>>(b->dts, b->partial, b->t_rem, b->dt);
-  for (int k = 0; k < 3; ++k) {
-    if (b->f32)
-      launch_points<float>(b->persist, b->grid_points, s, b->pts[k], b->n, b->pts_items, A[k], B[k], b->cnt);
-    else
-      launch_points<double>(b->persist, b->grid_points, s, b->pts[k], b->n, b->pts_items, A[k], B[k], b->cnt);
-    if (b->f32)
-      launch_cells<float>(b->persist, b->cshape, b->grid_cells, s, b->cls[k], b->n, b->cls_items, A[k], B[k],
-                          b->cnt);
-    else
-      launch_cells<double>(b->persist, b->cshape, b->grid_cells, s, b->cls[k], b->n, b->cls_items, A[k], B[k],
-                           b->cnt);
-  }
+  for (int k = 0; k < 3; ++k) enqueue_stage(b, k, A[k], B[k]);
   return bcheck(b, hipSuccess, "batch step launch");
 }
 
@@ -545,12 +610,7 @@ double time_stage0(af_mhd_batch* b, int reps) {
     e = hipEventRecord(e0, s);
     kb_dt_partial<<<b->grid_dt, BLK, 0, s>>>(b->dts, b->n, b->dt_items, b->partial);
     kb_dt_final<<<b->n, BLK, 0, s>>>(b->dts, b->partial, b->t_rem, b->dt);
-    if (b->f32) launch_points<float>(b->persist, b->grid_points, s, b->pts[0], b->n, b->pts_items, A0, B0, b->cnt);
-    else launch_points<double>(b->persist, b->grid_points, s, b->pts[0], b->n, b->pts_items, A0, B0, b->cnt);
-    if (b->f32)
-      launch_cells<float>(b->persist, b->cshape, b->grid_cells, s, b->cls[0], b->n, b->cls_items, A0, B0, b->cnt);
-    else
-      launch_cells<double>(b->persist, b->cshape, b->grid_cells, s, b->cls[0], b->n, b->cls_items, A0, B0, b->cnt);
+    enqueue_stage(b, 0, A0, B0);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -652,17 +712,26 @@ int af_mhd_batch_init(const af_mhd_params* p, int n, const af_mhd_state* states,
       b->cshape = cells[1] > cells[0] ? 1 : 0;
       rc = build_tables(b);
     }
-    if (rc == AF_OK) {
-      // launch mode of the whole batch: persistent or one item per workgroup
-      b->persist = true;
-      const double tp = time_stage0(b, 3);
-      b->persist = false;
-      const double tf = time_stage0(b, 3);
-      if (tp < 0.0 || tf < 0.0) rc = bcheck(b, hipErrorUnknown, "autotune (launch mode)");
-      b->persist = tp <= tf;
-      kb_zero_counters<<<1, 64, 0, b->stream>>>(b->cnt);
-      if (rc == AF_OK) rc = bcheck(b, hipStreamSynchronize(b->stream), "autotune");
+  }
+  if (rc == AF_OK && tune_table) {
+    // launch mode of the whole batch: the fastest of the three on stage 0
+    double best = -1.0;
+    int best_mode = AF_BATCH_FLAT;
+    for (int mode : {AF_BATCH_FUSED, AF_BATCH_PERSISTENT, AF_BATCH_FLAT}) {
+      b->mode = mode;
+      const double t = time_stage0(b, 3);
+      if (t < 0.0) {
+        rc = bcheck(b, hipErrorUnknown, "autotune (launch mode)");
+        break;
+      }
+      if (best < 0.0 || t < best) {
+        best = t;
+        best_mode = mode;
+      }
     }
+    b->mode = best_mode;
+    kb_zero_counters<<<1, 64, 0, b->stream>>>(b->cnt);
+    if (rc == AF_OK) rc = bcheck(b, hipStreamSynchronize(b->stream), "autotune");
   }
   if (rc != AF_OK) {
     batch_init_err = b->err;
@@ -719,11 +788,27 @@ int af_mhd_batch_counters(af_mhd_batch* b, af_mhd_stats_t* out) {
   return AF_OK;
 }
 
-int af_mhd_batch_launch_mode(const af_mhd_batch* b, int* persistent) {
-  if (!b || !persistent) return AF_EINVAL;
-  *persistent = b->persist ? 1 : 0;
+int af_mhd_batch_launch_mode(const af_mhd_batch* b, int* mode) {
+  if (!b || !mode) return AF_EINVAL;
+  *mode = b->mode;
   return AF_OK;
 }
+
+int af_mhd_batch_set_launch_mode(af_mhd_batch* b, int mode) {
+  if (!b) return AF_EINVAL;
+  if (mode != AF_BATCH_FLAT && mode != AF_BATCH_PERSISTENT && mode != AF_BATCH_FUSED)
+    return bfail(b, AF_EINVAL, "af_mhd_batch_set_launch_mode: unknown mode");
+  if (mode == b->mode) return AF_OK;
+  // the captured step is the old mode's: drop it, the next graph step records the new one
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->mode = mode;
+  b->err.clear();
+  return AF_OK;
+}
+
 
 void af_mhd_batch_destroy(af_mhd_batch* b) { delete b; }
 

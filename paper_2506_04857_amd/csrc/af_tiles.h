@@ -419,18 +419,20 @@ __device__ __forceinline__ void lean_fvs(R (*s)[PB][PB], int dir, int so, int sb
   P.divl += jl * sh;
 }
 
+// (tx, ty): the thread's place in the tile.  live = false runs the tile's
+// arithmetic and barriers but stores nothing and counts nothing (a
+// workgroup that runs two tiles side by side and has only one to do).
 template <class R>
 __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState un, MState out,
                                                  double* __restrict__ src, double dt, double ca, double cb,
                                                  Counters* cn, int bx, int by, R (*s)[PB][PB],
-                                                 double* __restrict__ wslot) {
+                                                 double* __restrict__ wslot, int tx, int ty, bool live) {
   constexpr bool F32 = IsF32<R>::value;
   double wm = 0.0;
   double* const wmax = wslot ? &wm : nullptr;
-  const int tx = threadIdx.x, ty = threadIdx.y;
   const int i0 = bx * (PB - 2) - 1, j0 = by * (PB - 2) - 1;
   const int i = clamp_pt(i0 + tx, g.nxp), j = clamp_pt(j0 + ty, g.nyp);
-  const bool inner = tx >= 1 && tx < PB - 1 && ty >= 1 && ty < PB - 1;
+  const bool inner = live && tx >= 1 && tx < PB - 1 && ty >= 1 && ty < PB - 1;
   const bool outV = inner && i0 + tx < g.nxp && j0 + ty < g.nyp;
   const bool outX = inner && i0 + tx < g.nxp && j0 + ty < g.ny;
   const bool outY = inner && i0 + tx < g.nx && j0 + ty < g.nyp;
@@ -529,7 +531,7 @@ __device__ __forceinline__ void points_tile_lean(const Geo& g, CState u, CState 
     const bool owner = inner && i0 + tx < g.nx && j0 + ty < g.ny;
     limit_centre(Uc, A, g.gm1, C, cn, owner);
     sts8(s, SC_, ty, tx, C);
-    if (owner) {
+    if (owner && src) {
       // the cell's nine-point source for the cell kernel, from the tile's
       // point values (in LDS since the barrier above) and this centre value
       auto Bat = [&](int a, int b, R& b1, R& b2) {
@@ -638,7 +640,8 @@ __device__ __forceinline__ void points_tile(const Geo& g, CState u, CState un, M
                                             double* __restrict__ src, double dt, double ca, double cb,
                                             Counters* cn, int bx, int by, R (*s)[PB][PB],
                                             double* __restrict__ wslot = nullptr) {
-  points_tile_lean<R>(g, u, un, out, src, dt, ca, cb, cn, bx, by, s, wslot);
+  points_tile_lean<R>(g, u, un, out, src, dt, ca, cb, cn, bx, by, s, wslot, (int)threadIdx.x, (int)threadIdx.y,
+                      true);
 }
 
 // ------------------------------------------------------ fused cell update
@@ -806,6 +809,8 @@ struct CellsLDS {
 };
 
 // One tile of the cell update: CBX x CBY threads, (CBX-3) x (CBY-3) cells.
+// src: the point kernel's nine-point sources, or null (every cell computes
+// its own from the stage input, as the ghost cells do).
 template <class R, int CBX, int CBY>
 __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double* __restrict__ src,
                                            const double* __restrict__ un, double* __restrict__ out, double dt,
@@ -869,7 +874,7 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   // now, in flight while the indicators are computed
   double A[NV], Sd[NV], w0[NV];
   ldA(g, u.a, i, j, A);
-  ldA(g, src, i, j, Sd);
+  if (src) ldA(g, src, i, j, Sd);
   ldV(g, u.v, i, j, w0);
   // 1b: indicators on [i0-1, i0+CBX) x [j0-1, j0+CBY)
   for (int it = tid; it < (CBX + 1) * (CBY + 1); it += CNT) {
@@ -896,7 +901,7 @@ __device__ __forceinline__ void cells_tile(const Geo& g, CState u, const double*
   // 2: nine-point source: the point kernel's for the grid's cells; a ghost
   //    cell across an outflow boundary (its mirrored stencil differs from
   //    its image's) computes its own
-  if ((g.bcx && (i < 0 || i >= g.nx)) || (g.bcy && (j < 0 || j >= g.ny))) {
+  if (!src || (g.bcx && (i < 0 || i >= g.nx)) || (g.bcy && (j < 0 || j >= g.ny))) {
     double C[NV];
     centre_value(g, u, i, j, C);
     cell_source(g, u, C, i, j, S);

@@ -93,6 +93,9 @@ def test_batch_host_side_argument_checks(lib):
     h = ctypes.c_void_p()
     assert L.af_mhd_batch_init(P, 3, None, None, None, None, 0, None, None, ctypes.byref(h)) == AF_EINVAL
     assert L.af_mhd_batch_step(None, 1) == AF_EINVAL
+    assert L.af_mhd_batch_set_launch_mode(None, 2) == AF_EINVAL
+    mode = ctypes.c_int()
+    assert L.af_mhd_batch_launch_mode(None, ctypes.byref(mode)) == AF_EINVAL
     assert b"bad argument" in L.af_mhd_batch_last_error(None)
 
 

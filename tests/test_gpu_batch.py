@@ -1,7 +1,8 @@
 """Batched ensembles through the C ABI: every instance of a batch (mixed
-sizes, boundaries and gamma, persistent or flat launches, any cell-tile
-shape, plain launches or hipGraph replays) must be bitwise equal to the
-single-grid context's run on that instance, step by step.
+sizes, boundaries and gamma; flat, persistent or fused launches -- the
+last one launch per stage whose cell tiles compute their own nine-point
+sources; any cell-tile shape, plain launches or hipGraph replays) must be bitwise equal to the single-grid context's run
+on that instance, step by step.
 
 Each DoF's arithmetic is the same in both paths and the dt reduction is a
 max (order-independent), so equality is exact.  The batch is also compared
@@ -61,12 +62,20 @@ def single_runs(af, probs, u0s, nsteps, flags):
 
 
 def check_batch(af, probs, nsteps, flags=0, use_graph=True, tune_table=None, force_mode=None):
+    """Bitwise equality with the single-grid runs, except in the fused mode,
+    whose cell tiles form their nine-point sources with their own instruction
+    selection (fused multiply-adds placed by the compiler in each context):
+    there every field within 1e-14 of the single-grid run's scale (1e-6 for
+    the FP32-bulk stage, whose sources are FP32 sums)."""
     import torch
     u0s = [I.sample(p) for p in probs]
     ref = single_runs(af, probs, u0s, nsteps, flags)
     states = [af.to_device(u) for u in u0s]
     b = af.Batch(probs, states, flags=flags, tune_table=tune_table)
-    say(f"[batch] n={len(probs)} flags={flags} graph={use_graph} persistent={b.persistent()} "
+    if force_mode is not None:
+        b.set_launch_mode(force_mode)
+    mode = b.launch_mode()  # with a tune table: the fastest of the three
+    say(f"[batch] n={len(probs)} flags={flags} graph={use_graph} mode={b.launch_mode()} "
         f"tiles={[b.tile(m) for m in range(len(probs))]}")
     for n in range(nsteps):
         b.step(use_graph=use_graph)
@@ -78,6 +87,15 @@ def check_batch(af, probs, nsteps, flags=0, use_graph=True, tune_table=None, for
         for m in range(len(probs)):
             got = af.to_host(states[m])
             want, dt_want = ref[m][n]
+            if mode == af.AF_BATCH_FUSED:
+                tol = 1e-6 if flags & af.AF_FLAG_FP32_BULK else 1e-14
+                assert abs(dts[m] - dt_want) <= 1e3 * tol * dt_want, f"step {n} instance {m}: dt {dts[m]!r}"
+                for a, w in zip(got, want):
+                    for c in range(8):
+                        scale = max(float(np.max(np.abs(w[c]))), 1e-300)
+                        err = float(np.max(np.abs(a[c] - w[c]))) / scale
+                        assert err <= tol, f"step {n} instance {m} ({probs[m].name}) field {c}: {err:.3e}"
+                continue
             assert dts[m] == dt_want, f"step {n} instance {m}: dt {dts[m]!r} vs {dt_want!r}"
             for a, w in zip(got, want):
                 assert np.array_equal(a, w), f"step {n} instance {m} ({probs[m].name}) differs"
@@ -97,6 +115,38 @@ def test_batch_plain_launches_equal_single_grid_runs(af):
 
 def test_batch_fp32_equals_single_grid_fp32(af):
     check_batch(af, mixed_problems(), 3, flags=af.AF_FLAG_FP32_BULK, use_graph=True)
+
+
+MODES = {"flat": 0, "persistent": 1, "fused": 2}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_batch_launch_modes_equal_single_grid_runs(af, mode):
+    # every launch mode, graph replays and plain launches, FP64 and FP32-bulk
+    check_batch(af, mixed_problems(), 3, use_graph=True, force_mode=MODES[mode])
+    check_batch(af, mixed_problems(), 1, use_graph=False, force_mode=MODES[mode])
+    check_batch(af, mixed_problems(), 2, flags=af.AF_FLAG_FP32_BULK, use_graph=True, force_mode=MODES[mode])
+
+
+def test_batch_mode_switch_recaptures_the_graph(af):
+    # a graph captured in one mode is dropped when the mode changes
+    import torch
+    probs = mixed_problems()
+    u0s = [I.sample(p) for p in probs]
+    ref = single_runs(af, probs, u0s, 3, 0)
+    states = [af.to_device(u) for u in u0s]
+    b = af.Batch(probs, states)
+    for n, mode in enumerate((MODES["persistent"], MODES["flat"], MODES["persistent"])):
+        b.set_launch_mode(mode)
+        assert b.launch_mode() == mode
+        b.step(use_graph=True)
+        torch.cuda.synchronize()
+        for m in range(len(probs)):
+            for a, w in zip(af.to_host(states[m]), ref[m][n][0]):
+                assert np.array_equal(a, w), f"step {n} (mode {mode}) instance {m} differs"
+    with pytest.raises(af.AfMhdError):
+        b.set_launch_mode(7)
+    b.close()
 
 
 def test_batch_autotune_table(af, tmp_path):
@@ -146,6 +196,7 @@ def test_batch_against_the_oracle(af, oracle, kind):
     u0s = [I.sample(p) for p in probs]
     states = [af.to_device(u) for u in u0s]
     b = af.Batch(probs, states)
+    b.set_launch_mode(af.AF_BATCH_FUSED)
     refs = list(u0s)
     worst = 0.0
     for n in range(nsteps):
