@@ -214,8 +214,13 @@ __device__ __forceinline__ void sts8(R (*s)[PB][PB], int base, int ty, int tx, c
 // values, 80 KB for the FP64 stage (two workgroups per CU), 40 KB for the
 // FP32-bulk one.  A point's flux, v_n and spectral radius in the family's
 // direction are rebuilt from its state and record with the operations of
-// eval_dir (for FP64 bit for bit).  The families run one per barrier pair in
-// the order b, c, a, d, which keeps at most two point accumulators live.
+// eval_dir (for FP64 bit for bit).  The families run in the order b, c, a,
+// d, which keeps at most two point accumulators live: b's records are
+// formed from the values the tile load brings and its line sums share the
+// centre-value phase (they read no centre value); c, a and d each take a
+// barrier pair (records, then line sums).  A point is finished (limiter,
+// SSP combination, store) after the next family's records, its U^n loaded
+// just before them.
 // FP32-bulk: states and records in FP32; a thread's own FP64 states (for the
 // records, whose pressure recovery is FP64, and for the finish) and its FP64
 // centre value stay in registers from the tile load.
