@@ -5,7 +5,8 @@
     derivatives of the same discrete stage, branches of the value):
     |<lam, J v> - <J^T lam, v>| <= 1e-10 sum |lam_i (J v)_i|, per input set
     and stage, on smooth, stirred-shock (scaling limiters, density box and
-    Newton roots active), Orszag-Tang and blast data;
+    Newton roots active), Orszag-Tang and blast data; and on the adjoint
+    workload's own 256^2 grid, mid-trajectory, from the oracle's stage inputs;
   * gradients of J = 1/2 sum (rho(T) - 1)^2 over several steps through
     torch.autograd with sqrt(n) checkpointing: against the tangent oracle run
     with the same dt sequence (1e-10) and central differences of the fast
@@ -109,6 +110,52 @@ def test_recorded_stage_and_dot_products(af, oracle, name, make):
             a_k = (0.75, 1.0 / 3.0)[k - 1]
             for x, y in zip(lnh, lam):
                 assert np.max(np.abs(x - a_k * y)) <= 1e-15 * np.max(np.abs(y))
+    adj.close()
+
+
+def test_workload_stages_at_full_size(af, oracle):
+    # The adjoint workload's grid itself (perturbed Alfven wave 256^2,
+    # periodic, kappa 1) at a state 40 steps into the oracle's own
+    # trajectory: each of the three stages recorded on the GPU from the
+    # oracle's stage inputs equals the oracle's stage (1e-11 per field), and
+    # its reverse satisfies the dot-product identity against the tangent
+    # oracle at the 1e-10 bar, all four input sets perturbed at once.  Both
+    # sides take every branch (the signs of phi3's div Bbar numerator, which
+    # sits at rounding level on this wave, included) from the same inputs,
+    # so the whole-trajectory comparison's rounding-level divergence does
+    # not enter.
+    import torch
+    prob = I.alfven_perturbed(256)
+    u0 = I.sample(prob)
+    for _ in range(40):
+        u0, _ = oracle.step(prob, u0)
+    dt = oracle.dt(prob, u0)
+    rng = np.random.default_rng(17)
+    adj = af.Adjoint(prob)
+    dt_dev = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    un_dev = af.to_device(u0)
+    uk = u0
+    for k in range(3):
+        ref = oracle.stage(prob, k, u0, uk, dt)
+        out = af.empty_state(prob)
+        tape = adj.new_tape()
+        uk_dev = af.to_device(uk)
+        adj.record(k, un_dev, uk_dev, out, dt_dev, tape)
+        lam = tuple(rng.standard_normal(a.shape) for a in u0)
+        ln = tuple(torch.zeros_like(t) for t in out)
+        lk = tuple(torch.zeros_like(t) for t in out)
+        adj.stage(k, uk_dev, tape, dt_dev, af.to_device(lam), ln if k else None, lk)
+        torch.cuda.synchronize()
+        fe = max(np.max(np.abs(a - b)) / np.max(np.abs(b)) for a, b in zip(af.to_host(out), ref))
+        lkh = af.to_host(lk)
+        z = tuple(np.zeros_like(a) for a in u0)
+        v = tuple(rng.standard_normal(a.shape) for a in u0)
+        _, d = oracle.tangent_stage(prob, k, u0, [v if k == 0 else z], uk, [v], dt)
+        err = abs(dot(lam, d[0]) - dot(lkh, v)) / absdot(lam, d[0])
+        say(f"[adjoint] workload 256^2 after 40 steps, k={k}: forward {fe:.1e} dot {err:.1e}")
+        assert fe <= 1e-11
+        assert err <= BAR
+        uk = ref
     adj.close()
 
 
