@@ -1,14 +1,18 @@
 """The measurement tooling on synthetic rocprofv3 CSV files (no GPU): the
 per-dispatch counter means, the copy-calibrated traffic per launch, the SQ
-summary and the bench's algorithmic byte counts."""
+summary, the bench's algorithmic byte counts and the committed summaries'
+commands."""
 import csv
 import io
+import os
 import sys
 from contextlib import redirect_stdout
 
 import pytest
 
 from paper_2506_04857_amd import rocprof_summary as rs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 HEAD = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size", "Kernel_Id",
         "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count",
@@ -117,3 +121,27 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_every_profile_summary_names_its_commands():
+    # Each rocprofv3 summary under profiles/ is short text that gives the
+    # full commands that made it (the profiler pass and the summariser), and
+    # those commands run committed files only.
+    import glob
+    import re
+    import subprocess
+    files = sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt")))
+    assert files
+    # committed files: from git where the checkout has its history, else
+    # the files present beside the tests
+    res = subprocess.run(["git", "ls-files"], cwd=ROOT, capture_output=True, text=True)
+    tracked = set(res.stdout.split()) if res.returncode == 0 else None
+    for path in files:
+        text = open(path).read()
+        name = os.path.basename(path)
+        assert len(text) < 16384, name
+        assert "rocprofv3 " in text and "rocprof_summary" in text, name
+        assert "_work" not in text, name
+        for script in re.findall(r"\$R/(\S+\.py)\b", text):
+            assert os.path.exists(os.path.join(ROOT, script)), (name, script)
+            assert tracked is None or script in tracked, (name, script)
